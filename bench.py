@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D2Q9 MRT + absorbing-layer step on one MI355X.
+
+Workload: a single 4096 x 4096 periodic lattice, FP32 deviation storage
+(base f^eq(rho0, u0)), uniform mean flow at Mach 0.2 in x, a seeded sum of
+32 Gaussian density pulses (amplitudes U[1e-4, 1e-3], half-widths U[4, 16]),
+a 64-cell quadratic sponge ramp to chi_max = 0.2 on all sides (separable
+form), S = (0, 0, 0, 1.9 x 6), n = m = 1/2. The headline variant is Type II;
+Types I and III are timed the same way and reported beside it.
+
+A step is one launch of the fused pull-stream + collide kernel over the whole
+lattice; diagnostics (FP64 reductions) run every 100 steps inside the timed
+region. Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "D2Q9 MRT+sponge MLUPS & %HBM peak; batched-served vs plain MLUPS, p99 latency"
+KERNEL_SRC = os.path.join(ROOT, "paper_1203_6350_amd", "csrc", "lbm_kernels.hip")
+DEVICE_HDR = os.path.join(ROOT, "paper_1203_6350_amd", "csrc", "lbm_device.h")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_f32_typeII_4096_pmc.txt")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in (KERNEL_SRC, DEVICE_HDR):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 --pmc summary,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    b = re.search(r"scaled_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
+    rho, ux, uy = fields
+    stream = torch.cuda.current_stream()
+    lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage=spec.storage,
+                      variant=spec.variant, s=spec.s, ux_base=spec.base_state[1],
+                      f16_scale=5e-4, stream=stream)
+    cx, cy = spec.chi_1d()
+    lat.set_sponge_separable(cx, cy, "max", spec.qref)
+    diag = torch.empty(7, dtype=torch.float64, device="cuda")
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    diag_after = set()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        lat.step(1)
+        ev[i + 1].record(stream)
+        if diag_every and (i + 1) % diag_every == 0:
+            lbm.lbm_diagnostics_dev(lat.h, diag)
+            diag_after.add(i + 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # per-launch durations of the step kernel alone (intervals that contain a
+    # diagnostics launch are left out)
+    durs = []
+    for i in range(steps):
+        if i in diag_after:
+            continue
+        durs.append(ev[i].elapsed_time(ev[i + 1]))
+    d = diag.cpu().numpy()
+    lat.close()
+    wall = t1 - t0
+    cells = spec.nx * spec.ny
+    return dict(wall_s=wall, ms_per_step=1e3 * wall / steps,
+                mlups=cells * steps / wall / 1e6,
+                kernel_ms=sum(durs) / len(durs), diag=[float(x) for x in d])
+
+
+def copy_bandwidth(lbm, torch, nbytes=2 << 30, reps=20):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.lbm_device_copy(b, a, nbytes, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        lbm.lbm_device_copy(b, a, nbytes, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(spec, fields, steps):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    rho, ux, uy = fields
+    f0 = oracle.feq_field(rho, ux, uy)
+    chi = spec.chi_2d()
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    oracle.step(f0, steps, s=spec.s, chi=chi, qref=spec.qref, variant=spec.variant,
+                nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": spec.nx * spec.ny * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": oracle.max_threads() if threads <= 0 else threads, "kind": "oracle",
+            "sample": "%dx%d workload, %d steps, Type %s, FP64, %.1f s" %
+                      (spec.nx, spec.ny, steps, spec.variant, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16"])
+    ap.add_argument("--variants", default="II,I,III")
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: every box here has one MI355X, so "
+              "--gpus %d is not run (multi-GPU sharding is a design note)." % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1203_6350_amd import lbm, workloads as wl
+
+    torch.cuda.set_device(0)
+    lbm.load()
+    variants = [v for v in args.variants.split(",") if v]
+    head = variants[0]
+    spec = wl.large_c2(variant=head, storage=args.storage, n=args.n)
+    print("bench: building %dx%d inputs" % (spec.nx, spec.ny), file=sys.stderr, flush=True)
+    fields = spec.fields()
+    eb = {"f64": 8, "f32": 4, "f16": 2}[args.storage]
+    bytes_per_cell = 18 * eb
+    cells = spec.nx * spec.ny
+
+    results = {}
+    for v in variants:
+        sv = wl.large_c2(variant=v, storage=args.storage, n=args.n)
+        k = args.steps if v == head else max(100, args.steps // 4)
+        print("bench: timing Type %s, %d steps" % (v, k), file=sys.stderr, flush=True)
+        results[v] = time_variant(lbm, wl, torch, sv, fields, k, args.warmup)
+    r = results[head]
+    achieved = bytes_per_cell * cells / (r["kernel_ms"] * 1e-3) / 1e9
+    copy_gbps = None if args.no_copy else copy_bandwidth(lbm, torch)
+
+    out = {
+        "metric": METRIC,
+        "value": r["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f64": "f64", "f16": "f32 (f16 storage)"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 MRT + Type %s sponge, %dx%d periodic, %s deviation storage, "
+                               "Mach 0.2 mean flow, 32 seeded Gaussian pulses, 64-cell quadratic "
+                               "ramp chi_max=0.2" % (head, spec.nx, spec.ny, args.storage.upper()),
+                   "nx": spec.nx, "ny": spec.ny, "variant": head, "storage": args.storage,
+                   "diagnostics_every": 100},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS,
+                     "traffic": counter_traffic() if args.storage == "f32" and args.n == 4096
+                     and head == "II" else None,
+                     "algorithmic_bytes_per_launch": bytes_per_cell * cells,
+                     "kernel_ms": r["kernel_ms"]},
+        "per_variant": {v: {"mlups": x["mlups"], "kernel_ms": x["kernel_ms"],
+                            "achieved_gbps": bytes_per_cell * cells / (x["kernel_ms"] * 1e-3) / 1e9,
+                            "nonfinite_cells": x["diag"][6], "max_dev": x["diag"][5]}
+                        for v, x in results.items()},
+        "copy_kernel_gbps": copy_gbps,
+    }
+    if copy_gbps:
+        out["roofline"]["frac_of_copy"] = achieved / copy_gbps
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec, fields, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * lbm.h -- C ABI of liblbm.so: a D2Q9 multi-relaxation-time lattice
+ * Boltzmann time stepper with the absorbing-layer damping terms of
+ * H. Xu and P. Sagaut, "Analysis of the absorbing layers for the
+ * weakly-compressible lattice Boltzmann schemes" (arXiv:1203.6350),
+ * running on AMD Instinct MI355X (gfx950) through HIP.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Velocities are ordered as the columns of the paper's D2Q9 transform
+ *   matrix M (Appendix A.1): c0=(0,0) c1=(1,0) c2=(0,1) c3=(-1,0) c4=(0,-1)
+ *   c5=(1,1) c6=(-1,1) c7=(-1,-1) c8=(1,-1); delta t = 1; c_s^2 = 1/3.
+ * - Fields are row-major [ny][nx] (x fastest); populations are [9][ny][nx].
+ * - The lattice is periodic in x and y (lattice closure, Section 2.1).
+ * - The state observed through this API is the pre-collision population
+ *   f(x, t) of eq. blbs; one step is collision (with damping) followed by
+ *   streaming, f_i(x + c_i, t + 1) = f'_i(x, t).
+ * - Host pointers are read or written during the call only; the library
+ *   never keeps them. Device pointers (the *_dev calls) are used on the
+ *   handle's stream and must stay valid until that work completes.
+ * - Every function returns LBM_OK (0) or a negative status; no C++ exception
+ *   crosses the ABI. lbm_last_error() returns a thread-local description of
+ *   the last failure on the calling thread.
+ * - A handle must be used by one thread at a time; distinct handles may run
+ *   concurrently on distinct streams.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* bad argument (size, range, NULL, non-finite) */
+#define LBM_ENOMEM (-2)    /* device or host allocation failed             */
+#define LBM_EDEVICE (-3)   /* HIP runtime error or no usable gfx950 device */
+#define LBM_EUNSTABLE (-4) /* the instability detector tripped             */
+#define LBM_ESTATE (-5)    /* call not valid in the handle's current state */
+
+/* ---- population storage ---------------------------------------------- */
+/* All modes store deviations g_i = f_i - f_i^base from the base state
+ * f^base = f^eq(rho_base, u_base) (u_base = 0 gives the rest weights
+ * w_i rho_base). */
+#define LBM_STORAGE_F64 0 /* FP64 storage, FP64 arithmetic                */
+#define LBM_STORAGE_F32 1 /* FP32 storage, FP32 arithmetic                */
+#define LBM_STORAGE_F16 2 /* FP16 storage of g_i / (w_i f16_scale), FP32 arithmetic */
+
+/* ---- damping variants (Section 2.2, Gamma = chi I, eq. eq:gamma) ------ */
+#define LBM_VARIANT_NONE 0 /* plain scheme, eq. blbs                       */
+#define LBM_VARIANT_I 1    /* f^ref = f^eq(q_ref), f* = f (Sec. 2.2.1)     */
+#define LBM_VARIANT_II 2   /* f^ref = f^eq(q_ref), f* = f^eq(rho*,u*) (2.2.2) */
+#define LBM_VARIANT_III 3  /* f^ref = f^L(q_ref), f* = f^L(rho*,u*) (2.2.3) */
+
+/* ---- separable sponge combination ------------------------------------ */
+#define LBM_COMBINE_MAX 0 /* chi(x,y) = max(chi_x[x], chi_y[y]) */
+#define LBM_COMBINE_SUM 1 /* chi(x,y) = chi_x[x] + chi_y[y]     */
+
+typedef struct lbm_config {
+  int64_t nx, ny;      /* lattice size, each >= 1; nx * ny * 9 < 2^31     */
+  double rho_base;     /* base state of the stored deviations, > 0         */
+  double ux_base, uy_base;
+  double s[9];         /* diagonal of S in moment order (rho, jx, jy, e,
+                          eps, qx, qy, pxx, pxy), each in [0, 2]
+                          (Section 2.1); BGK is s[k] = s for all k         */
+  double shift_n;      /* n of rho* = sum f + n dt sum F (Sec. 2.2)       */
+  double shift_m;      /* m of rho* u* = sum c f + m dt sum c F            */
+  int32_t storage;     /* LBM_STORAGE_*                                    */
+  int32_t variant;     /* LBM_VARIANT_*                                    */
+  double f16_scale;    /* amplitude scale sigma of LBM_STORAGE_F16, > 0    */
+  void *stream;        /* hipStream_t for all work of the handle; NULL =
+                          the default stream                               */
+} lbm_config;
+
+/* Reference (far-field) state q_ref = (rho^f, u^f), eqs. eq:reff, Sec. 3.2. */
+typedef struct lbm_qref {
+  double rho_f, ux_f, uy_f;
+} lbm_qref;
+
+typedef struct lbm_info {
+  int64_t nx, ny;
+  int64_t pitch;        /* elements between rows                            */
+  int64_t plane_stride; /* elements between population planes               */
+  int64_t steps_done;   /* steps taken since create / set_populations       */
+  int32_t storage, variant;
+  int32_t elem_bytes;   /* bytes per stored population element              */
+  int32_t chi_mode;     /* 0 none, 1 2-D field, 2 separable                 */
+  size_t device_bytes;  /* device memory held for both lattices + sponge    */
+} lbm_info;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Create a lattice and set f = f^eq(rho, u) (the initial state of the
+ * pulse set-up, eq. pulseprofile). rho, ux, uy: host [ny][nx] FP64, or NULL
+ * for the uniform base state. The library allocates and owns the device
+ * memory. The sponge starts at chi = 0 with q_ref = base state.
+ * Errors: EINVAL (sizes, rates outside [0,2], rho_base <= 0, non-finite or
+ * non-positive rho), EDEVICE, ENOMEM. */
+int lbm_create(const lbm_config *cfg, const double *rho, const double *ux,
+               const double *uy, lbm_handle **out);
+
+/* Bytes of device memory one lattice pair needs (both lattices, padded). */
+int lbm_required_bytes(const lbm_config *cfg, size_t *bytes);
+
+/* As lbm_create, but the two population buffers are caller-owned device
+ * memory (for instance torch tensors), each at least
+ * lbm_required_bytes()/2 bytes and 256-byte aligned; they must outlive the
+ * handle. */
+int lbm_create_ext(const lbm_config *cfg, const double *rho, const double *ux,
+                   const double *uy, void *dev_buf_a, void *dev_buf_b,
+                   size_t bytes_each, lbm_handle **out);
+
+/* Sponge strength chi(x) >= 0 as a full host field [ny][nx] (NULL means
+ * chi = 0 everywhere) and the uniform reference state q (NULL keeps the
+ * current one). Values are copied. sigma = chi sigma~ profiles of eq.
+ * normalizedsigma and Table tab:sigma are built by the caller.
+ * Errors: EINVAL (negative or non-finite chi, rho_f <= 0). */
+int lbm_set_sponge(lbm_handle *h, const double *chi, const lbm_qref *q);
+
+/* Separable sponge chi(x, y) = combine(chi_x[x], chi_y[y]) with host arrays
+ * chi_x[nx], chi_y[ny] (either may be NULL for zeros); adds no per-cell
+ * memory traffic. combine: LBM_COMBINE_*. */
+int lbm_set_sponge_separable(lbm_handle *h, const double *chi_x,
+                             const double *chi_y, int32_t combine,
+                             const lbm_qref *q);
+
+/* Enqueue n >= 0 time steps (collision with the damping term of the
+ * handle's variant, then streaming) on the handle's stream and return
+ * without waiting. */
+int lbm_step(lbm_handle *h, int64_t n);
+
+/* Wait for all work of the handle. */
+int lbm_sync(lbm_handle *h);
+
+/* Raw pre-collision moments rho = sum_i f_i, u = sum_i c_i f_i / rho
+ * (eq. q-macro) into host arrays [ny][nx] FP64 (any may be NULL).
+ * Synchronises. */
+int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy);
+
+/* As lbm_moments into device arrays [ny][nx] FP64, asynchronous. */
+int lbm_moments_dev(lbm_handle *h, double *rho, double *ux, double *uy);
+
+/* FP64 reductions over the lattice of the pre-collision state, with
+ * deviations taken from the base state:
+ *   out[0] = sum drho, out[1] = sum djx, out[2] = sum djy,
+ *   out[3] = sum drho^2, out[4] = sum |dj|^2,
+ *   out[5] = max_i,x |f_i - f_i^base|, out[6] = number of cells holding a
+ *   non-finite population.
+ * E_L2 of Section 4.1 with rho_ref = rho_base is sqrt(out[3] / sum rho_ref^2).
+ * Deterministic (fixed reduction order). Synchronises. */
+int lbm_diagnostics(lbm_handle *h, double out[7]);
+
+/* As lbm_diagnostics into a device array of 7 doubles, asynchronous on the
+ * handle's stream. */
+int lbm_diagnostics_dev(lbm_handle *h, double *out7_dev);
+
+/* Full pre-collision populations f = f^base + g in FP64, host [9][ny][nx].
+ * Synchronises. */
+int lbm_get_populations(lbm_handle *h, double *f);
+
+/* Replace the state by host populations f [9][ny][nx] FP64 (checkpoint
+ * restore); resets steps_done to 0. Synchronises. */
+int lbm_set_populations(lbm_handle *h, const double *f);
+
+/* Raw checkpoint of the stored state: the nine planes of the current lattice
+ * exactly as held on the device (storage precision, pull layout) plus the
+ * step count. lbm_state_bytes gives the size; lbm_save_state copies into a
+ * host buffer of that size, lbm_load_state restores it, so that a resumed
+ * run continues bit for bit. Both synchronise. */
+int lbm_state_bytes(lbm_handle *h, size_t *bytes);
+int lbm_save_state(lbm_handle *h, void *host, size_t bytes);
+int lbm_load_state(lbm_handle *h, const void *host, size_t bytes);
+
+int lbm_get_info(lbm_handle *h, lbm_info *info);
+
+/* Release all resources of the handle; NULL is accepted. */
+void lbm_destroy(lbm_handle *h);
+
+const char *lbm_last_error(void);
+
+/* ---- Von Neumann analysis (Section 3.2, eqs. eq:linearized, sec:matrix) --
+ * For the scheme linearised about f^eq(q_ref) with uniform chi, computes per
+ * wavenumber k = (kx, ky) the amplification matrix with the streaming phase
+ * restored, G(k) = diag(exp(-i k.c_j)) M^-1 A_m M, where
+ * A_m = I + S (J D P - I) - chi X is the moment-space Jacobian of the
+ * collision (P: projection on rho, jx, jy; D: derivative of rho*, j*;
+ * J: derivative of m^eq; X = I for Type I, J D P for Type II, L D P for
+ * Type III with L the derivative of m^L), and its eigenvalues
+ * lambda = exp(-i omega), sorted by (-|lambda|, arg lambda).
+ * All arithmetic is FP64 on the device. */
+typedef struct lbm_vn_params {
+  double s[9];
+  double shift_n, shift_m;
+  double chi;
+  double rho_f, ux_f, uy_f;
+  int32_t variant;
+  int32_t pad_;
+} lbm_vn_params;
+
+/* kx, ky: nk wavenumbers; eig: [nk][9][2] (re, im); G: NULL or
+ * [nk][9][9][2]. Pointers are host memory. Synchronous. */
+int vn_amplification(const lbm_vn_params *p, int64_t nk, const double *kx,
+                     const double *ky, double *eig, double *G);
+
+/* Device-pointer variant, asynchronous on stream (hipStream_t, may be NULL):
+ * nparams parameter sets, each evaluated on the same nk wavenumbers;
+ * params is host memory, kx/ky/eig/G are device memory with eig
+ * [nparams][nk][9][2] and G NULL or [nparams][nk][9][9][2]. */
+int vn_amplification_dev(const lbm_vn_params *params, int64_t nparams,
+                         int64_t nk, const double *kx, const double *ky,
+                         double *eig, double *G, void *stream);
+
+/* ---- device bandwidth probe ------------------------------------------
+ * Copies `bytes` (multiple of 16) from src to dst device memory with the
+ * library's streaming copy kernel on `stream`; used to calibrate the
+ * achievable HBM bandwidth and the traffic counters. */
+int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,582 @@
+// lbm_api.cpp -- C ABI of liblbm (declared in include/lbm.h).
+//
+// Owns the device state of one lattice (two population lattices, the sponge
+// arrays, diagnostic scratch), validates arguments, and enqueues the kernels
+// of lbm_kernels.hip / lbm_vn.hip on the handle's stream. No arithmetic of
+// the method runs on the host: the host only converts parameters and copies
+// inputs and outputs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();  // clear the sticky launch error
+  return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+int check_device(int *dev_out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(LBM_EDEVICE, std::string("liblbm is built for gfx950, device is ") +
+                                 prop.gcnArchName);
+  if (dev_out) *dev_out = dev;
+  return LBM_OK;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_config user;
+  lbm::StepConfig cfg;
+  lbm_qref q;
+  hipStream_t stream = nullptr;
+  void *lat[2] = {nullptr, nullptr};
+  bool own_lat = true;
+  int cur = 0;
+  void *chi_field = nullptr;  // compute type [ny][pitch]
+  void *chi_x = nullptr;      // compute type [nx]
+  void *chi_y = nullptr;      // compute type [ny]
+  double *diag_partials = nullptr;
+  double *diag_out = nullptr;
+  int64_t steps = 0;
+  size_t lat_bytes = 0;
+  int device = 0;
+};
+
+namespace {
+
+int validate_config(const lbm_config *c) {
+  if (!c) return fail(LBM_EINVAL, "config is NULL");
+  if (c->nx < 1 || c->ny < 1) return fail(LBM_EINVAL, "nx and ny must be >= 1");
+  if (c->nx > (1 << 30) || c->ny > (1 << 30) || c->nx * c->ny >= (int64_t(1) << 31))
+    return fail(LBM_EINVAL, "nx * ny must be below 2^31");
+  if (!(c->rho_base > 0) || !is_fin(c->rho_base))
+    return fail(LBM_EINVAL, "rho_base must be finite and > 0");
+  if (!is_fin(c->ux_base) || !is_fin(c->uy_base))
+    return fail(LBM_EINVAL, "base velocity must be finite");
+  for (int k = 0; k < 9; ++k)
+    if (!(c->s[k] >= 0.0 && c->s[k] <= 2.0))
+      return fail(LBM_EINVAL, "relaxation rates must lie in [0, 2]");
+  if (!is_fin(c->shift_n) || !is_fin(c->shift_m) || c->shift_n < 0 || c->shift_m < 0)
+    return fail(LBM_EINVAL, "shift parameters must be finite and >= 0");
+  if (c->storage < LBM_STORAGE_F64 || c->storage > LBM_STORAGE_F16)
+    return fail(LBM_EINVAL, "unknown storage mode");
+  if (c->variant < LBM_VARIANT_NONE || c->variant > LBM_VARIANT_III)
+    return fail(LBM_EINVAL, "unknown damping variant");
+  if (c->storage == LBM_STORAGE_F16 && !(c->f16_scale > 0 && is_fin(c->f16_scale)))
+    return fail(LBM_EINVAL, "f16_scale must be finite and > 0");
+  return LBM_OK;
+}
+
+void layout(const lbm_config *c, int64_t *pitch, int64_t *ps, size_t *lat_bytes) {
+  const int eb = lbm::elem_bytes_of(c->storage);
+  *pitch = c->nx;
+  // planes start on 256-byte boundaries
+  *ps = round_up(c->nx * c->ny, 256 / eb);
+  *lat_bytes = (size_t)(*ps) * 9 * eb;
+}
+
+void fill_cfg(lbm_handle *h) {
+  lbm::StepConfig &s = h->cfg;
+  const lbm_config &u = h->user;
+  s.nx = (int)u.nx;
+  s.ny = (int)u.ny;
+  s.storage = u.storage;
+  s.variant = u.variant;
+  for (int k = 0; k < 9; ++k) s.s[k] = u.s[k];
+  s.n = u.shift_n;
+  s.m = u.shift_m;
+  s.rho_b = u.rho_base;
+  s.ubx = u.ux_base;
+  s.uby = u.uy_base;
+  s.f16_scale = u.storage == LBM_STORAGE_F16 ? u.f16_scale : 1.0;
+  // q_ref - base in FP64 (argument conversion)
+  s.dcf[0] = h->q.rho_f - u.rho_base;
+  s.dcf[1] = (h->q.rho_f - u.rho_base) * h->q.ux_f + u.rho_base * (h->q.ux_f - u.ux_base);
+  s.dcf[2] = (h->q.rho_f - u.rho_base) * h->q.uy_f + u.rho_base * (h->q.uy_f - u.uy_base);
+  s.chi_field = h->chi_field;
+  s.chi_x = h->chi_x;
+  s.chi_y = h->chi_y;
+}
+
+// Upload an FP64 host array converted to the compute type of the handle.
+int upload_compute(lbm_handle *h, const double *src, size_t n, void **dst) {
+  const bool f64 = h->user.storage == LBM_STORAGE_F64;
+  const size_t eb = f64 ? 8 : 4;
+  if (!*dst) HIP_TRY(hipMalloc(dst, n * eb), "hipMalloc(sponge)");
+  std::vector<float> tmp;
+  const void *p = src;
+  if (!f64) {
+    tmp.resize(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+    p = tmp.data();
+  }
+  HIP_TRY(hipMemcpyAsync(*dst, p, n * eb, hipMemcpyHostToDevice, h->stream),
+          "hipMemcpy(sponge)");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+void free_sponge(lbm_handle *h) {
+  if (h->chi_field) (void)hipFree(h->chi_field);
+  if (h->chi_x) (void)hipFree(h->chi_x);
+  if (h->chi_y) (void)hipFree(h->chi_y);
+  h->chi_field = h->chi_x = h->chi_y = nullptr;
+}
+
+int check_qref(const lbm_qref *q) {
+  if (!q) return LBM_OK;
+  if (!(q->rho_f > 0) || !is_fin(q->rho_f) || !is_fin(q->ux_f) || !is_fin(q->uy_f))
+    return fail(LBM_EINVAL, "q_ref must be finite with rho_f > 0");
+  return LBM_OK;
+}
+
+int check_chi(const double *a, size_t n) {
+  if (!a) return LBM_OK;
+  for (size_t i = 0; i < n; ++i)
+    if (!(a[i] >= 0.0) || !is_fin(a[i]))
+      return fail(LBM_EINVAL, "chi must be finite and >= 0");
+  return LBM_OK;
+}
+
+int init_state(lbm_handle *h, const double *rho, const double *ux,
+               const double *uy) {
+  const int64_t N = h->user.nx * h->user.ny;
+  double *d = nullptr;
+  if (rho) {
+    for (int64_t i = 0; i < N; ++i)
+      if (!(rho[i] > 0) || !is_fin(rho[i]) || (ux && !is_fin(ux[i])) || (uy && !is_fin(uy[i])))
+        return fail(LBM_EINVAL, "initial fields must be finite with rho > 0");
+    HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 3 * N), "hipMalloc(init)");
+    std::vector<double> zero;
+    if (!ux || !uy) zero.assign(N, 0.0);
+    hipError_t e = hipMemcpy(d, rho, sizeof(double) * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(d + N, ux ? ux : zero.data(), sizeof(double) * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(d + 2 * N, uy ? uy : zero.data(), sizeof(double) * N, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(e, "hipMemcpy(init)");
+    }
+  }
+  hipError_t e = lbm::launch_init(h->cfg, d, d ? d + N : nullptr, d ? d + 2 * N : nullptr,
+                                  h->lat[0], h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (d) (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  h->cur = 0;
+  h->steps = 0;
+  return LBM_OK;
+}
+
+int create_common(const lbm_config *cfg, const double *rho, const double *ux,
+                  const double *uy, void *buf_a, void *buf_b, size_t bytes_each,
+                  lbm_handle **out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  int dev = 0;
+  rc = check_device(&dev);
+  if (rc) return rc;
+  lbm_handle *h = new (std::nothrow) lbm_handle();
+  if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+  h->user = *cfg;
+  h->device = dev;
+  h->stream = (hipStream_t)cfg->stream;
+  h->q = lbm_qref{cfg->rho_base, cfg->ux_base, cfg->uy_base};
+  int64_t pitch, ps;
+  layout(cfg, &pitch, &ps, &h->lat_bytes);
+  h->cfg.pitch = pitch;
+  h->cfg.plane_stride = ps;
+  h->cfg.chi_mode = lbm::CHI_ZERO;
+  h->cfg.tile = 0;
+  if (buf_a) {
+    if (!buf_b || bytes_each < h->lat_bytes || ((uintptr_t)buf_a & 255) ||
+        ((uintptr_t)buf_b & 255)) {
+      delete h;
+      return fail(LBM_EINVAL, "caller buffers too small or not 256-byte aligned");
+    }
+    h->lat[0] = buf_a;
+    h->lat[1] = buf_b;
+    h->own_lat = false;
+  } else {
+    for (int k = 0; k < 2; ++k) {
+      hipError_t e = hipMalloc(&h->lat[k], h->lat_bytes);
+      if (e != hipSuccess) {
+        lbm_destroy(h);
+        return hip_fail(e, "hipMalloc(lattice)");
+      }
+    }
+  }
+  hipError_t e = hipMalloc((void **)&h->diag_partials, lbm::diag_partials_bytes(h->cfg));
+  if (e == hipSuccess) e = hipMalloc((void **)&h->diag_out, 8 * sizeof(double));
+  if (e != hipSuccess) {
+    lbm_destroy(h);
+    return hip_fail(e, "hipMalloc(diagnostics)");
+  }
+  fill_cfg(h);
+  rc = init_state(h, rho, ux, uy);
+  if (rc) {
+    lbm_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_required_bytes(const lbm_config *cfg, size_t *bytes) {
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  int64_t pitch, ps;
+  size_t lb;
+  layout(cfg, &pitch, &ps, &lb);
+  *bytes = 2 * lb;
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_config *cfg, const double *rho, const double *ux,
+               const double *uy, lbm_handle **out) {
+  return create_common(cfg, rho, ux, uy, nullptr, nullptr, 0, out);
+}
+
+int lbm_create_ext(const lbm_config *cfg, const double *rho, const double *ux,
+                   const double *uy, void *dev_buf_a, void *dev_buf_b,
+                   size_t bytes_each, lbm_handle **out) {
+  if (!dev_buf_a || !dev_buf_b) return fail(LBM_EINVAL, "device buffers are NULL");
+  return create_common(cfg, rho, ux, uy, dev_buf_a, dev_buf_b, bytes_each, out);
+}
+
+int lbm_set_sponge(lbm_handle *h, const double *chi, const lbm_qref *q) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int rc = check_qref(q);
+  if (rc) return rc;
+  const size_t N = (size_t)(h->user.nx * h->user.ny);
+  rc = check_chi(chi, N);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  free_sponge(h);
+  if (chi) {
+    // field stored with the lattice row pitch
+    std::vector<double> padded((size_t)(h->cfg.pitch * h->user.ny), 0.0);
+    for (int64_t y = 0; y < h->user.ny; ++y)
+      std::memcpy(&padded[(size_t)(y * h->cfg.pitch)], chi + y * h->user.nx,
+                  sizeof(double) * h->user.nx);
+    rc = upload_compute(h, padded.data(), padded.size(), &h->chi_field);
+    if (rc) return rc;
+    h->cfg.chi_mode = lbm::CHI_FIELD;
+  } else {
+    h->cfg.chi_mode = lbm::CHI_ZERO;
+  }
+  if (q) h->q = *q;
+  fill_cfg(h);
+  return LBM_OK;
+}
+
+int lbm_set_sponge_separable(lbm_handle *h, const double *chi_x,
+                             const double *chi_y, int32_t combine,
+                             const lbm_qref *q) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (combine != LBM_COMBINE_MAX && combine != LBM_COMBINE_SUM)
+    return fail(LBM_EINVAL, "unknown combine mode");
+  int rc = check_qref(q);
+  if (rc) return rc;
+  rc = check_chi(chi_x, (size_t)h->user.nx);
+  if (!rc) rc = check_chi(chi_y, (size_t)h->user.ny);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  free_sponge(h);
+  if (chi_x || chi_y) {
+    std::vector<double> ax(h->user.nx, 0.0), ay(h->user.ny, 0.0);
+    if (chi_x) std::memcpy(ax.data(), chi_x, sizeof(double) * h->user.nx);
+    if (chi_y) std::memcpy(ay.data(), chi_y, sizeof(double) * h->user.ny);
+    rc = upload_compute(h, ax.data(), ax.size(), &h->chi_x);
+    if (!rc) rc = upload_compute(h, ay.data(), ay.size(), &h->chi_y);
+    if (rc) return rc;
+    h->cfg.chi_mode = combine == LBM_COMBINE_MAX ? lbm::CHI_SEP_MAX : lbm::CHI_SEP_SUM;
+  } else {
+    h->cfg.chi_mode = lbm::CHI_ZERO;
+  }
+  if (q) h->q = *q;
+  fill_cfg(h);
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle *h, int64_t n) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  for (int64_t k = 0; k < n; ++k) {
+    hipError_t e = lbm::launch_step(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel");
+    h->cur = 1 - h->cur;
+    h->steps += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_handle *h) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_moments_dev(lbm_handle *h, double *rho, double *ux, double *uy) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  hipError_t e = lbm::launch_moments(h->cfg, h->lat[h->cur], rho, ux, uy, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "moments kernel");
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  const int64_t N = h->user.nx * h->user.ny;
+  double *d = nullptr;
+  HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 3 * N), "hipMalloc(moments)");
+  hipError_t e = lbm::launch_moments(h->cfg, h->lat[h->cur], d, d + N, d + 2 * N, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && rho) e = hipMemcpy(rho, d, sizeof(double) * N, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && ux) e = hipMemcpy(ux, d + N, sizeof(double) * N, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && uy) e = hipMemcpy(uy, d + 2 * N, sizeof(double) * N, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_handle *h, double out[7]) {
+  if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+  hipError_t e = lbm::launch_diagnostics(h->cfg, h->lat[h->cur], h->diag_partials,
+                                         h->diag_out, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, h->diag_out, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics");
+  return LBM_OK;
+}
+
+int lbm_diagnostics_dev(lbm_handle *h, double *out7_dev) {
+  if (!h || !out7_dev) return fail(LBM_EINVAL, "NULL argument");
+  hipError_t e = lbm::launch_diagnostics(h->cfg, h->lat[h->cur], h->diag_partials,
+                                         out7_dev, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics");
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle *h, double *f) {
+  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  const int64_t N = h->user.nx * h->user.ny;
+  double *d = nullptr;
+  HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 9 * N), "hipMalloc(populations)");
+  hipError_t e = lbm::launch_get_populations(h->cfg, h->lat[h->cur], d, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(f, d, sizeof(double) * 9 * N, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "get_populations");
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_handle *h, const double *f) {
+  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  const int64_t N = h->user.nx * h->user.ny;
+  for (int64_t i = 0; i < 9 * N; ++i)
+    if (!is_fin(f[i])) return fail(LBM_EINVAL, "populations must be finite");
+  double *d = nullptr;
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 9 * N), "hipMalloc(populations)");
+  hipError_t e = hipMemcpy(d, f, sizeof(double) * 9 * N, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = lbm::launch_set_populations(h->cfg, d, h->lat[0], h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "set_populations");
+  h->cur = 0;
+  h->steps = 0;
+  return LBM_OK;
+}
+
+int lbm_state_bytes(lbm_handle *h, size_t *bytes) {
+  if (!h || !bytes) return fail(LBM_EINVAL, "NULL argument");
+  *bytes = h->lat_bytes + sizeof(int64_t);
+  return LBM_OK;
+}
+
+int lbm_save_state(lbm_handle *h, void *host, size_t bytes) {
+  if (!h || !host) return fail(LBM_EINVAL, "NULL argument");
+  if (bytes != h->lat_bytes + sizeof(int64_t)) return fail(LBM_EINVAL, "state buffer size mismatch");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(host, h->lat[h->cur], h->lat_bytes, hipMemcpyDeviceToHost), "hipMemcpy(state)");
+  std::memcpy((char *)host + h->lat_bytes, &h->steps, sizeof(int64_t));
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_handle *h, const void *host, size_t bytes) {
+  if (!h || !host) return fail(LBM_EINVAL, "NULL argument");
+  if (bytes != h->lat_bytes + sizeof(int64_t)) return fail(LBM_EINVAL, "state buffer size mismatch");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(h->lat[0], host, h->lat_bytes, hipMemcpyHostToDevice), "hipMemcpy(state)");
+  h->cur = 0;
+  std::memcpy(&h->steps, (const char *)host + h->lat_bytes, sizeof(int64_t));
+  return LBM_OK;
+}
+
+int lbm_get_info(lbm_handle *h, lbm_info *info) {
+  if (!h || !info) return fail(LBM_EINVAL, "NULL argument");
+  info->nx = h->user.nx;
+  info->ny = h->user.ny;
+  info->pitch = h->cfg.pitch;
+  info->plane_stride = h->cfg.plane_stride;
+  info->steps_done = h->steps;
+  info->storage = h->user.storage;
+  info->variant = h->user.variant;
+  info->elem_bytes = lbm::elem_bytes_of(h->user.storage);
+  info->chi_mode = h->cfg.chi_mode;
+  info->device_bytes = 2 * h->lat_bytes;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  if (h->own_lat)
+    for (int k = 0; k < 2; ++k)
+      if (h->lat[k]) (void)hipFree(h->lat[k]);
+  free_sponge(h);
+  if (h->diag_partials) (void)hipFree(h->diag_partials);
+  if (h->diag_out) (void)hipFree(h->diag_out);
+  delete h;
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src || (bytes & 15)) return fail(LBM_EINVAL, "copy needs non-NULL pointers and bytes % 16 == 0");
+  hipError_t e = lbm::launch_copy(dst, src, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "copy kernel");
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int validate_vn(const lbm_vn_params *params, int64_t nparams) {
+  if (nparams > 65535) return fail(LBM_EINVAL, "at most 65535 parameter sets per call");
+  for (int64_t p = 0; p < nparams; ++p) {
+    const lbm_vn_params &v = params[p];
+    for (int k = 0; k < 9; ++k)
+      if (!(v.s[k] >= 0 && v.s[k] <= 2)) return fail(LBM_EINVAL, "rates must lie in [0, 2]");
+    if (!(v.chi >= 0) || !is_fin(v.chi) || !(v.rho_f > 0) || !is_fin(v.ux_f) ||
+        !is_fin(v.uy_f) || !is_fin(v.shift_n) || !is_fin(v.shift_m))
+      return fail(LBM_EINVAL, "bad Von Neumann parameters");
+    if (v.variant < 0 || v.variant > 3) return fail(LBM_EINVAL, "unknown variant");
+  }
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int vn_amplification_dev(const lbm_vn_params *params, int64_t nparams, int64_t nk,
+                         const double *kx, const double *ky, double *eig,
+                         double *G, void *stream) {
+  if (!params || nparams < 1 || nk < 0 || (nk > 0 && (!kx || !ky || !eig)))
+    return fail(LBM_EINVAL, "bad Von Neumann arguments");
+  int rc0 = validate_vn(params, nparams);
+  if (rc0) return rc0;
+  if (nk == 0) return LBM_OK;
+  int rc = check_device(nullptr);
+  if (rc) return rc;
+  std::vector<lbm::VnParamsDev> hp(nparams);
+  for (int64_t p = 0; p < nparams; ++p) {
+    for (int k = 0; k < 9; ++k) hp[p].s[k] = params[p].s[k];
+    hp[p].n = params[p].shift_n;
+    hp[p].m = params[p].shift_m;
+    hp[p].chi = params[p].chi;
+    hp[p].rho_f = params[p].rho_f;
+    hp[p].ux_f = params[p].ux_f;
+    hp[p].uy_f = params[p].uy_f;
+    hp[p].variant = params[p].variant;
+    hp[p].pad_ = 0;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  lbm::VnParamsDev *dp = nullptr;
+  HIP_TRY(hipMalloc((void **)&dp, sizeof(lbm::VnParamsDev) * nparams), "hipMalloc(vn params)");
+  hipError_t e = hipMemcpyAsync(dp, hp.data(), sizeof(lbm::VnParamsDev) * nparams,
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = lbm::launch_vn(dp, (int)nparams, nk, kx, ky, eig, G, s);
+  // the parameter block must live until the kernel has read it
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dp);
+  if (e != hipSuccess) return hip_fail(e, "Von Neumann kernel");
+  return LBM_OK;
+}
+
+int vn_amplification(const lbm_vn_params *p, int64_t nk, const double *kx,
+                     const double *ky, double *eig, double *G) {
+  if (!p || nk < 0 || (nk > 0 && (!kx || !ky || !eig)))
+    return fail(LBM_EINVAL, "bad Von Neumann arguments");
+  int rc = validate_vn(p, 1);
+  if (rc) return rc;
+  if (nk == 0) return LBM_OK;
+  rc = check_device(nullptr);
+  if (rc) return rc;
+  double *d = nullptr;
+  const size_t nkb = sizeof(double) * nk;
+  const size_t eb = nkb * 18, gb = G ? nkb * 162 : 0;
+  HIP_TRY(hipMalloc((void **)&d, 2 * nkb + eb + gb), "hipMalloc(vn)");
+  hipError_t e = hipMemcpy(d, kx, nkb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d + nk, ky, nkb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "hipMemcpy(vn)");
+  }
+  double *de = d + 2 * nk, *dg = G ? de + 18 * nk : nullptr;
+  rc = vn_amplification_dev(p, 1, nk, d, d + nk, de, dg, nullptr);
+  if (rc == LBM_OK) {
+    e = hipMemcpy(eig, de, eb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && G) e = hipMemcpy(G, dg, gb, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(vn)");
+  }
+  (void)hipFree(d);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// lbm_internal.h -- host-side structures shared by the C ABI and the kernel
+// launchers of liblbm. Not installed; the public interface is include/lbm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Everything a step kernel needs, in FP64; launchers convert to the compute
+// precision of the storage mode.
+struct StepConfig {
+  int nx, ny;
+  int64_t pitch;         // elements between rows
+  int64_t plane_stride;  // elements between population planes
+  int storage;           // LBM_STORAGE_*
+  int variant;           // LBM_VARIANT_*
+  int chi_mode;          // ChiMode
+  double s[9];
+  double n, m;
+  double rho_b, ubx, uby;
+  double dcf[3];         // q_ref - base, conserved moments
+  double f16_scale;
+  const void *chi_field; // [ny][pitch] compute type, CHI_FIELD
+  const void *chi_x;     // [nx] compute type
+  const void *chi_y;     // [ny] compute type
+  int tile;              // kernel variant chosen by the tuner (0 = generic)
+};
+
+// Launchers (lbm_kernels.hip). All enqueue on `stream` and return the HIP
+// status of the launch.
+hipError_t launch_step(const StepConfig &c, const void *src, void *dst,
+                       hipStream_t stream);
+hipError_t launch_init(const StepConfig &c, const double *rho,
+                       const double *ux, const double *uy, void *dst,
+                       hipStream_t stream);
+hipError_t launch_set_populations(const StepConfig &c, const double *f,
+                                  void *dst, hipStream_t stream);
+hipError_t launch_get_populations(const StepConfig &c, const void *src,
+                                  double *f, hipStream_t stream);
+hipError_t launch_moments(const StepConfig &c, const void *src, double *rho,
+                          double *ux, double *uy, hipStream_t stream);
+// partials: device scratch of at least diag_partials_bytes(c) bytes;
+// out7: device array of 7 doubles.
+size_t diag_partials_bytes(const StepConfig &c);
+hipError_t launch_diagnostics(const StepConfig &c, const void *src,
+                              double *partials, double *out7,
+                              hipStream_t stream);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes,
+                       hipStream_t stream);
+int elem_bytes_of(int storage);
+
+// Von Neumann (lbm_vn.hip).
+struct VnParamsDev {
+  double s[9];
+  double n, m, chi, rho_f, ux_f, uy_f;
+  int variant;
+  int pad_;
+};
+hipError_t launch_vn(const VnParamsDev *params_dev, int nparams, int64_t nk,
+                     const double *kx, const double *ky, double *eig,
+                     double *G, hipStream_t stream);
+
+}  // namespace lbm

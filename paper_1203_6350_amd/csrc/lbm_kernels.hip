@@ -1,0 +1,494 @@
+// lbm_kernels.hip -- HIP kernels of the D2Q9 MRT + absorbing-layer step for
+// gfx950 (Xu & Sagaut, arXiv:1203.6350) and their launchers.
+//
+// Memory layout (HBM): two lattices A and B, each nine population planes of
+// ny rows x pitch elements (x fastest), planes plane_stride elements apart.
+// A lattice holds post-collision deviations g'(x, t) at the cell where they
+// were produced; a step pulls g_i(x, t+1) = g'_i(x - c_i, t) (streaming),
+// collides at x and writes g'(x, t+1) into the other lattice at x. So every
+// element is read once and written once per step, the writes are fully
+// coalesced and the reads of the six x-shifted planes are offset by one
+// element.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+template <typename S>
+struct Lat {
+  typedef typename Store<S>::C C;
+  int nx, ny;
+  int64_t pitch, ps;
+  C scale[9], inv_scale[9];
+};
+
+template <typename S>
+static Lat<S> make_lat(const StepConfig &c) {
+  typedef typename Store<S>::C C;
+  Lat<S> L;
+  L.nx = c.nx;
+  L.ny = c.ny;
+  L.pitch = c.pitch;
+  L.ps = c.plane_stride;
+  for (int i = 0; i < 9; ++i) {
+    const double sc = c.storage == 2 ? w_of(i) * c.f16_scale : 1.0;
+    L.scale[i] = C(sc);
+    L.inv_scale[i] = C(1.0 / sc);
+  }
+  return L;
+}
+
+template <typename C>
+static CollideParams<C> make_params(const StepConfig &c) {
+  CollideParams<C> p;
+  for (int k = 0; k < 9; ++k) p.s[k] = C(c.s[k]);
+  p.n = C(c.n);
+  p.m = C(c.m);
+  p.rho_b = C(c.rho_b);
+  p.ubx = C(c.ubx);
+  p.uby = C(c.uby);
+  p.dcf0 = C(c.dcf[0]);
+  p.dcf1 = C(c.dcf[1]);
+  p.dcf2 = C(c.dcf[2]);
+  return p;
+}
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+  return a < 0 ? a + n : (a >= n ? a - n : a);
+}
+
+// ---------------------------------------------------------------- step
+// Generic kernel: one cell per thread, a block covers BX consecutive cells of
+// one row; blocks are numbered row-major so consecutive blocks (which the
+// hardware spreads over the XCDs) stream consecutive memory.
+template <typename S, int VAR, int CHI, int BX>
+__global__ __launch_bounds__(BX) void step_generic(
+    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
+    CollideParams<typename Store<S>::C> p,
+    const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix,
+    const typename Store<S>::C *__restrict__ chiy) {
+  typedef typename Store<S>::C C;
+  const int bpr = (L.nx + BX - 1) / BX;
+  const int y = blockIdx.x / bpr;
+  const int x = (blockIdx.x - y * bpr) * BX + threadIdx.x;
+  if (x >= L.nx) return;
+  const int xm = x == 0 ? L.nx - 1 : x - 1;
+  const int xp = x == L.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? L.ny - 1 : y - 1;
+  const int yp = y == L.ny - 1 ? 0 : y + 1;
+  const int64_t r0 = (int64_t)y * L.pitch, rm = (int64_t)ym * L.pitch,
+                rp = (int64_t)yp * L.pitch;
+  const int64_t ps = L.ps;
+  C g[9];
+  // pull: g_i(x) <- g'_i(x - c_i)
+  g[0] = Store<S>::load(src + 0 * ps + r0 + x, L.scale[0]);
+  g[1] = Store<S>::load(src + 1 * ps + r0 + xm, L.scale[1]);
+  g[2] = Store<S>::load(src + 2 * ps + rm + x, L.scale[2]);
+  g[3] = Store<S>::load(src + 3 * ps + r0 + xp, L.scale[3]);
+  g[4] = Store<S>::load(src + 4 * ps + rp + x, L.scale[4]);
+  g[5] = Store<S>::load(src + 5 * ps + rm + xm, L.scale[5]);
+  g[6] = Store<S>::load(src + 6 * ps + rm + xp, L.scale[6]);
+  g[7] = Store<S>::load(src + 7 * ps + rp + xp, L.scale[7]);
+  g[8] = Store<S>::load(src + 8 * ps + rp + xm, L.scale[8]);
+  const C chi = chi_at<C, CHI>(chi_field, chix, chiy, r0 + x, x, y);
+  collide<C, VAR>(g, chi, p);
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    Store<S>::store(dst + i * ps + r0 + x, g[i], L.inv_scale[i]);
+}
+
+template <typename S, int VAR, int CHI>
+static hipError_t launch_step_t(const StepConfig &c, const void *src,
+                                void *dst, hipStream_t stream) {
+  typedef typename Store<S>::C C;
+  Lat<S> L = make_lat<S>(c);
+  CollideParams<C> p = make_params<C>(c);
+  constexpr int BX = 256;
+  const int64_t blocks = (int64_t)((c.nx + BX - 1) / BX) * c.ny;
+  step_generic<S, VAR, CHI, BX><<<dim3((unsigned)blocks), dim3(BX), 0, stream>>>(
+      (const S *)src, (S *)dst, L, p, (const C *)c.chi_field,
+      (const C *)c.chi_x, (const C *)c.chi_y);
+  return hipGetLastError();
+}
+
+template <typename S, int VAR>
+static hipError_t dispatch_chi(const StepConfig &c, const void *src, void *dst,
+                               hipStream_t s) {
+  switch (c.chi_mode) {
+    case CHI_ZERO: return launch_step_t<S, VAR, CHI_ZERO>(c, src, dst, s);
+    case CHI_FIELD: return launch_step_t<S, VAR, CHI_FIELD>(c, src, dst, s);
+    case CHI_SEP_MAX: return launch_step_t<S, VAR, CHI_SEP_MAX>(c, src, dst, s);
+    case CHI_SEP_SUM: return launch_step_t<S, VAR, CHI_SEP_SUM>(c, src, dst, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename S>
+static hipError_t dispatch_var(const StepConfig &c, const void *src, void *dst,
+                               hipStream_t s) {
+  switch (c.variant) {
+    case V_NONE: return dispatch_chi<S, V_NONE>(c, src, dst, s);
+    case V_I: return dispatch_chi<S, V_I>(c, src, dst, s);
+    case V_II: return dispatch_chi<S, V_II>(c, src, dst, s);
+    case V_III: return dispatch_chi<S, V_III>(c, src, dst, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(const StepConfig &c, const void *src, void *dst,
+                       hipStream_t stream) {
+  switch (c.storage) {
+    case 0: return dispatch_var<double>(c, src, dst, stream);
+    case 1: return dispatch_var<float>(c, src, dst, stream);
+    case 2: return dispatch_var<__half>(c, src, dst, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+int elem_bytes_of(int storage) {
+  return storage == 0 ? 8 : (storage == 1 ? 4 : 2);
+}
+
+// ---------------------------------------------------------------- FP64 helpers
+// f^eq_i(rho, j) - f^eq_i(rho_b, j_b) in FP64, every term O(drho, dj).
+// f^eq_i = w_i [rho + 3 c.j + 9/2 (c.j)^2/rho - 3/2 |j|^2/rho].
+__device__ __forceinline__ double feq_dev_i(int i, double dr, double djx,
+                                            double djy, double rho_b,
+                                            double ubx, double uby) {
+  const double rho = rho_b + dr;
+  const double cx = cx_of(i), cy = cy_of(i);
+  const double dJ = cx * djx + cy * djy;   // d(c.j)
+  const double Ub = cx * ubx + cy * uby;   // c.u_b
+  const double vJ = dJ - Ub * dr;
+  const double dq_c = 2.0 * Ub * dJ - Ub * Ub * dr + vJ * vJ / rho;  // d((c.j)^2/rho)
+  const double vx = djx - ubx * dr, vy = djy - uby * dr;
+  const double dq_x = 2.0 * ubx * djx - ubx * ubx * dr + vx * vx / rho;
+  const double dq_y = 2.0 * uby * djy - uby * uby * dr + vy * vy / rho;
+  return w_of(i) * (dr + 3.0 * dJ + 4.5 * dq_c - 1.5 * (dq_x + dq_y));
+}
+
+__device__ __forceinline__ double fbase_i(int i, double rho_b, double ubx,
+                                          double uby) {
+  const double cu = cx_of(i) * ubx + cy_of(i) * uby;
+  const double u2 = ubx * ubx + uby * uby;
+  return w_of(i) * rho_b * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * u2);
+}
+
+template <typename S>
+__device__ __forceinline__ void store_dev(S *p, double v, double inv_scale);
+template <>
+__device__ __forceinline__ void store_dev<double>(double *p, double v, double) {
+  *p = v;
+}
+template <>
+__device__ __forceinline__ void store_dev<float>(float *p, double v, double) {
+  *p = (float)v;
+}
+template <>
+__device__ __forceinline__ void store_dev<__half>(__half *p, double v,
+                                                  double inv_scale) {
+  // FP64 -> FP32 -> FP16; the scale keeps values in the normal range
+  *p = __float2half_rn((float)(v * inv_scale));
+}
+
+template <typename S>
+__device__ __forceinline__ double load_dev(const S *p, double scale);
+template <>
+__device__ __forceinline__ double load_dev<double>(const double *p, double) {
+  return *p;
+}
+template <>
+__device__ __forceinline__ double load_dev<float>(const float *p, double) {
+  return (double)*p;
+}
+template <>
+__device__ __forceinline__ double load_dev<__half>(const __half *p,
+                                                   double scale) {
+  return (double)((float)__half2float(*p) * (float)scale);
+}
+
+struct DevLat {
+  int nx, ny;
+  int64_t pitch, ps;
+  double rho_b, ubx, uby;
+  double scale[9], inv_scale[9];
+};
+
+static DevLat make_devlat(const StepConfig &c) {
+  DevLat d;
+  d.nx = c.nx;
+  d.ny = c.ny;
+  d.pitch = c.pitch;
+  d.ps = c.plane_stride;
+  d.rho_b = c.rho_b;
+  d.ubx = c.ubx;
+  d.uby = c.uby;
+  for (int i = 0; i < 9; ++i) {
+    d.scale[i] = c.storage == 2 ? w_of(i) * c.f16_scale : 1.0;
+    d.inv_scale[i] = 1.0 / d.scale[i];
+  }
+  return d;
+}
+
+// ---------------------------------------------------------------- init
+// Storage location x holds, for direction i, the deviation that the next pull
+// brings to cell x + c_i: g'_i(x) = f^eq_i(rho, u at x + c_i) - f^base_i.
+template <typename S>
+__global__ void init_kernel(DevLat L, const double *__restrict__ rho,
+                            const double *__restrict__ ux,
+                            const double *__restrict__ uy, S *__restrict__ dst) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= (int64_t)L.nx * L.ny) return;
+  const int y = (int)(cell / L.nx), x = (int)(cell - (int64_t)y * L.nx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int xs = wrapi(x + cx_of(i), L.nx), ys = wrapi(y + cy_of(i), L.ny);
+    const int64_t src = (int64_t)ys * L.nx + xs;
+    double dr = 0.0, djx = 0.0, djy = 0.0;
+    if (rho) {
+      dr = rho[src] - L.rho_b;
+      // j - j_b = drho u + rho_b (u - u_b)
+      djx = dr * ux[src] + L.rho_b * (ux[src] - L.ubx);
+      djy = dr * uy[src] + L.rho_b * (uy[src] - L.uby);
+    }
+    const double v = feq_dev_i(i, dr, djx, djy, L.rho_b, L.ubx, L.uby);
+    store_dev<S>(dst + i * L.ps + (int64_t)y * L.pitch + x, v, L.inv_scale[i]);
+  }
+}
+
+// f: [9][ny][nx] full FP64 populations (pre-collision) -> storage.
+template <typename S>
+__global__ void setpop_kernel(DevLat L, const double *__restrict__ f,
+                              S *__restrict__ dst) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)L.nx * L.ny;
+  if (cell >= N) return;
+  const int y = (int)(cell / L.nx), x = (int)(cell - (int64_t)y * L.nx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int xs = wrapi(x + cx_of(i), L.nx), ys = wrapi(y + cy_of(i), L.ny);
+    const double v = f[i * N + (int64_t)ys * L.nx + xs] -
+                     fbase_i(i, L.rho_b, L.ubx, L.uby);
+    store_dev<S>(dst + i * L.ps + (int64_t)y * L.pitch + x, v, L.inv_scale[i]);
+  }
+}
+
+template <typename S>
+__global__ void getpop_kernel(DevLat L, const S *__restrict__ src,
+                              double *__restrict__ f) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)L.nx * L.ny;
+  if (cell >= N) return;
+  const int y = (int)(cell / L.nx), x = (int)(cell - (int64_t)y * L.nx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int xs = wrapi(x - cx_of(i), L.nx), ys = wrapi(y - cy_of(i), L.ny);
+    const double g = load_dev<S>(src + i * L.ps + (int64_t)ys * L.pitch + xs,
+                                 L.scale[i]);
+    f[i * N + cell] = fbase_i(i, L.rho_b, L.ubx, L.uby) + g;
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void gather_dev(const DevLat &L, const S *src,
+                                           int x, int y, double g[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int xs = wrapi(x - cx_of(i), L.nx), ys = wrapi(y - cy_of(i), L.ny);
+    g[i] = load_dev<S>(src + i * L.ps + (int64_t)ys * L.pitch + xs, L.scale[i]);
+  }
+}
+
+template <typename S>
+__global__ void moments_kernel(DevLat L, const S *__restrict__ src,
+                               double *__restrict__ rho, double *__restrict__ ux,
+                               double *__restrict__ uy) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= (int64_t)L.nx * L.ny) return;
+  const int y = (int)(cell / L.nx), x = (int)(cell - (int64_t)y * L.nx);
+  double g[9];
+  gather_dev<S>(L, src, x, y, g);
+  double dr = 0.0, djx = 0.0, djy = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    dr += g[i];
+    djx += cx_of(i) * g[i];
+    djy += cy_of(i) * g[i];
+  }
+  const double r = L.rho_b + dr;
+  if (rho) rho[cell] = r;
+  if (ux) ux[cell] = (L.rho_b * L.ubx + djx) / r;
+  if (uy) uy[cell] = (L.rho_b * L.uby + djy) / r;
+}
+
+// ---------------------------------------------------------------- diagnostics
+constexpr int DIAG_BLOCKS = 1024;
+constexpr int DIAG_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <typename S>
+__global__ __launch_bounds__(DIAG_THREADS) void diag_kernel(
+    DevLat L, const S *__restrict__ src, double *__restrict__ partials) {
+  const int64_t N = (int64_t)L.nx * L.ny;
+  const int64_t stride = (int64_t)DIAG_BLOCKS * DIAG_THREADS;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t cell = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x;
+       cell < N; cell += stride) {
+    const int y = (int)(cell / L.nx), x = (int)(cell - (int64_t)y * L.nx);
+    double g[9];
+    gather_dev<S>(L, src, x, y, g);
+    double dr = 0.0, djx = 0.0, djy = 0.0, mx = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      dr += g[i];
+      djx += cx_of(i) * g[i];
+      djy += cy_of(i) * g[i];
+      finite = finite && __builtin_isfinite(g[i]);
+      mx = fmax(mx, fabs(g[i]));
+    }
+    acc[0] += dr;
+    acc[1] += djx;
+    acc[2] += djy;
+    acc[3] += dr * dr;
+    acc[4] += djx * djx + djy * djy;
+    acc[5] = fmax(acc[5], mx);
+    acc[6] += finite ? 0.0 : 1.0;
+  }
+  __shared__ double red[DIAG_THREADS / 64][7];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double v = k == 5 ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    double v = red[0][k];
+    for (int w = 1; w < DIAG_THREADS / 64; ++w)
+      v = k == 5 ? fmax(v, red[w][k]) : v + red[w][k];
+    partials[(int64_t)blockIdx.x * 7 + k] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void diag_final_kernel(
+    const double *__restrict__ partials, double *__restrict__ out) {
+  // one wave; lane l sums blocks l, l + 64, ... in order, then a fixed tree
+  const int lane = threadIdx.x;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = lane; b < DIAG_BLOCKS; b += 64)
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      acc[k] = k == 5 ? fmax(acc[k], partials[b * 7 + k]) : acc[k] + partials[b * 7 + k];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double v = k == 5 ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lane == 0) out[k] = v;
+  }
+}
+
+size_t diag_partials_bytes(const StepConfig &) {
+  return sizeof(double) * 7 * DIAG_BLOCKS;
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename F>
+static hipError_t by_storage(int storage, F &&f) {
+  switch (storage) {
+    case 0: return f((double *)nullptr);
+    case 1: return f((float *)nullptr);
+    case 2: return f((__half *)nullptr);
+  }
+  return hipErrorInvalidValue;
+}
+
+static unsigned cell_blocks(const StepConfig &c) {
+  return (unsigned)(((int64_t)c.nx * c.ny + 255) / 256);
+}
+
+hipError_t launch_init(const StepConfig &c, const double *rho,
+                       const double *ux, const double *uy, void *dst,
+                       hipStream_t stream) {
+  DevLat L = make_devlat(c);
+  return by_storage(c.storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    init_kernel<S><<<cell_blocks(c), 256, 0, stream>>>(L, rho, ux, uy, (S *)dst);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_set_populations(const StepConfig &c, const double *f,
+                                  void *dst, hipStream_t stream) {
+  DevLat L = make_devlat(c);
+  return by_storage(c.storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    setpop_kernel<S><<<cell_blocks(c), 256, 0, stream>>>(L, f, (S *)dst);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_get_populations(const StepConfig &c, const void *src,
+                                  double *f, hipStream_t stream) {
+  DevLat L = make_devlat(c);
+  return by_storage(c.storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    getpop_kernel<S><<<cell_blocks(c), 256, 0, stream>>>(L, (const S *)src, f);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_moments(const StepConfig &c, const void *src, double *rho,
+                          double *ux, double *uy, hipStream_t stream) {
+  DevLat L = make_devlat(c);
+  return by_storage(c.storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    moments_kernel<S><<<cell_blocks(c), 256, 0, stream>>>(L, (const S *)src, rho, ux, uy);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_diagnostics(const StepConfig &c, const void *src,
+                              double *partials, double *out7,
+                              hipStream_t stream) {
+  DevLat L = make_devlat(c);
+  hipError_t e = by_storage(c.storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    diag_kernel<S><<<DIAG_BLOCKS, DIAG_THREADS, 0, stream>>>(L, (const S *)src, partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  diag_final_kernel<<<1, 64, 0, stream>>>(partials, out7);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- copy probe
+__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src,
+                                                   float4 *__restrict__ dst,
+                                                   int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes,
+                       hipStream_t stream) {
+  const int64_t n = (int64_t)(bytes / 16);
+  const int64_t want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+  copy_kernel<<<blocks, 256, 0, stream>>>((const float4 *)src, (float4 *)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,394 @@
+"""ctypes binding of liblbm.so (include/lbm.h): the same entry points under
+the same names, with numpy arrays marshalled to host pointers and torch
+tensors (or raw integers) to device pointers and streams.
+
+There is no fallback: if the HIP library or a gfx950 device is missing every
+call raises ``LbmError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+VARIANT = {"none": 0, "I": 1, "II": 2, "III": 3}
+COMBINE = {"max": 0, "sum": 1}
+_CODE_NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTABLE", -5: "ESTATE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_CODE_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class lbm_config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("rho_base", ctypes.c_double), ("ux_base", ctypes.c_double),
+                ("uy_base", ctypes.c_double), ("s", ctypes.c_double * 9),
+                ("shift_n", ctypes.c_double), ("shift_m", ctypes.c_double),
+                ("storage", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("f16_scale", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class lbm_qref(ctypes.Structure):
+    _fields_ = [("rho_f", ctypes.c_double), ("ux_f", ctypes.c_double), ("uy_f", ctypes.c_double)]
+
+
+class lbm_info(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("pitch", ctypes.c_int64),
+                ("plane_stride", ctypes.c_int64), ("steps_done", ctypes.c_int64),
+                ("storage", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("elem_bytes", ctypes.c_int32), ("chi_mode", ctypes.c_int32),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+class lbm_vn_params(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_double * 9), ("shift_n", ctypes.c_double),
+                ("shift_m", ctypes.c_double), ("chi", ctypes.c_double),
+                ("rho_f", ctypes.c_double), ("ux_f", ctypes.c_double),
+                ("uy_f", ctypes.c_double), ("variant", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_H = ctypes.c_void_p
+
+
+def load(path: str | None = None):
+    """Load liblbm.so (torch is imported first so that both share one HIP
+    runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (brings the process's HIP runtime)
+    except Exception:
+        pass
+    p = path or os.environ.get("LBM_LIB", LIB_PATH)
+    if not os.path.exists(p):
+        raise LbmError(LBM_EDEVICE, "liblbm.so not built at %s (run __graft_entry__.build())" % p)
+    L = ctypes.CDLL(p)
+    i64, i32, vp, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+    sig = {
+        "lbm_create": [ctypes.POINTER(lbm_config), _DP, _DP, _DP, ctypes.POINTER(_H)],
+        "lbm_required_bytes": [ctypes.POINTER(lbm_config), ctypes.POINTER(sz)],
+        "lbm_create_ext": [ctypes.POINTER(lbm_config), _DP, _DP, _DP, vp, vp, sz, ctypes.POINTER(_H)],
+        "lbm_set_sponge": [_H, _DP, ctypes.POINTER(lbm_qref)],
+        "lbm_set_sponge_separable": [_H, _DP, _DP, i32, ctypes.POINTER(lbm_qref)],
+        "lbm_step": [_H, i64],
+        "lbm_sync": [_H],
+        "lbm_moments": [_H, _DP, _DP, _DP],
+        "lbm_moments_dev": [_H, vp, vp, vp],
+        "lbm_diagnostics": [_H, _DP],
+        "lbm_diagnostics_dev": [_H, vp],
+        "lbm_get_populations": [_H, _DP],
+        "lbm_set_populations": [_H, _DP],
+        "lbm_get_info": [_H, ctypes.POINTER(lbm_info)],
+        "lbm_state_bytes": [_H, ctypes.POINTER(sz)],
+        "lbm_save_state": [_H, vp, sz],
+        "lbm_load_state": [_H, vp, sz],
+        "vn_amplification": [ctypes.POINTER(lbm_vn_params), i64, _DP, _DP, _DP, _DP],
+        "vn_amplification_dev": [ctypes.POINTER(lbm_vn_params), i64, i64, vp, vp, vp, vp, vp],
+        "lbm_device_copy": [vp, vp, sz, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.lbm_destroy.argtypes = [_H]
+    L.lbm_destroy.restype = None
+    L.lbm_last_error.argtypes = []
+    L.lbm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error()
+        raise LbmError(rc, msg.decode() if msg else "")
+
+
+def _host(a, n=None):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and arr.size != n:
+        raise ValueError("expected %d values, got %d" % (n, arr.size))
+    return arr, arr.ctypes.data_as(_DP)
+
+
+def _dev(t):
+    """Device pointer of a torch tensor, an int address, or None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def make_config(nx, ny, *, s=(0, 0, 0, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9), storage="f32",
+                variant="II", rho_base=1.0, ux_base=0.0, uy_base=0.0, shift_n=0.5,
+                shift_m=0.5, f16_scale=1e-3, stream=None):
+    c = lbm_config()
+    c.nx, c.ny = int(nx), int(ny)
+    c.rho_base, c.ux_base, c.uy_base = float(rho_base), float(ux_base), float(uy_base)
+    for k in range(9):
+        c.s[k] = float(s[k])
+    c.shift_n, c.shift_m = float(shift_n), float(shift_m)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
+    c.f16_scale = float(f16_scale)
+    c.stream = _stream_ptr(stream)
+    return c
+
+
+# ---------------------------------------------------------------- entry points
+
+def lbm_create(cfg, rho=None, ux=None, uy=None):
+    L = load()
+    n = cfg.nx * cfg.ny
+    _r, pr = _host(rho, n)
+    _u, pu = _host(ux, n)
+    _v, pv = _host(uy, n)
+    h = _H()
+    _check(L.lbm_create(ctypes.byref(cfg), pr, pu, pv, ctypes.byref(h)))
+    return h
+
+
+def lbm_required_bytes(cfg):
+    b = ctypes.c_size_t()
+    _check(load().lbm_required_bytes(ctypes.byref(cfg), ctypes.byref(b)))
+    return b.value
+
+
+def lbm_create_ext(cfg, buf_a, buf_b, rho=None, ux=None, uy=None):
+    """Create on caller-owned device buffers (e.g. torch uint8 tensors)."""
+    L = load()
+    n = cfg.nx * cfg.ny
+    _r, pr = _host(rho, n)
+    _u, pu = _host(ux, n)
+    _v, pv = _host(uy, n)
+    each = min(buf_a.numel() * buf_a.element_size(), buf_b.numel() * buf_b.element_size())
+    h = _H()
+    _check(L.lbm_create_ext(ctypes.byref(cfg), pr, pu, pv, _dev(buf_a), _dev(buf_b), each,
+                            ctypes.byref(h)))
+    return h
+
+
+def _qref(q):
+    if q is None:
+        return None
+    qq = lbm_qref(float(q[0]), float(q[1]), float(q[2]))
+    return ctypes.byref(qq)
+
+
+def lbm_set_sponge(h, chi=None, qref=None, *, nx=None, ny=None):
+    _c, pc = _host(chi)
+    _check(load().lbm_set_sponge(h, pc, _qref(qref)))
+
+
+def lbm_set_sponge_separable(h, chi_x=None, chi_y=None, combine="max", qref=None):
+    _a, pa = _host(chi_x)
+    _b, pb = _host(chi_y)
+    cm = COMBINE[combine] if isinstance(combine, str) else int(combine)
+    _check(load().lbm_set_sponge_separable(h, pa, pb, cm, _qref(qref)))
+
+
+def lbm_step(h, n=1):
+    _check(load().lbm_step(h, int(n)))
+
+
+def lbm_sync(h):
+    _check(load().lbm_sync(h))
+
+
+def lbm_get_info(h):
+    info = lbm_info()
+    _check(load().lbm_get_info(h, ctypes.byref(info)))
+    return info
+
+
+def lbm_moments(h):
+    info = lbm_get_info(h)
+    shape = (info.ny, info.nx)
+    rho, ux, uy = (np.empty(shape) for _ in range(3))
+    _check(load().lbm_moments(h, rho.ctypes.data_as(_DP), ux.ctypes.data_as(_DP),
+                              uy.ctypes.data_as(_DP)))
+    return rho, ux, uy
+
+
+def lbm_moments_dev(h, rho, ux, uy):
+    _check(load().lbm_moments_dev(h, _dev(rho), _dev(ux), _dev(uy)))
+
+
+def lbm_diagnostics(h):
+    out = np.empty(7)
+    _check(load().lbm_diagnostics(h, out.ctypes.data_as(_DP)))
+    return out
+
+
+def lbm_diagnostics_dev(h, out7):
+    _check(load().lbm_diagnostics_dev(h, _dev(out7)))
+
+
+def lbm_get_populations(h):
+    info = lbm_get_info(h)
+    f = np.empty((9, info.ny, info.nx))
+    _check(load().lbm_get_populations(h, f.ctypes.data_as(_DP)))
+    return f
+
+
+def lbm_set_populations(h, f):
+    info = lbm_get_info(h)
+    _a, pa = _host(f, 9 * info.nx * info.ny)
+    _check(load().lbm_set_populations(h, pa))
+
+
+def lbm_state_bytes(h):
+    b = ctypes.c_size_t()
+    _check(load().lbm_state_bytes(h, ctypes.byref(b)))
+    return b.value
+
+
+def lbm_save_state(h):
+    buf = np.empty(lbm_state_bytes(h), dtype=np.uint8)
+    _check(load().lbm_save_state(h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+    return buf
+
+
+def lbm_load_state(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(load().lbm_load_state(h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+
+
+def lbm_destroy(h):
+    if h is not None and load() is not None:
+        load().lbm_destroy(h)
+
+
+def lbm_last_error():
+    m = load().lbm_last_error()
+    return m.decode() if m else ""
+
+
+def _vn_params(p):
+    v = lbm_vn_params()
+    for k in range(9):
+        v.s[k] = float(p["s"][k])
+    v.shift_n = float(p.get("n", 0.5))
+    v.shift_m = float(p.get("m", 0.5))
+    v.chi = float(p["chi"])
+    q = p.get("qref", (1.0, 0.0, 0.0))
+    v.rho_f, v.ux_f, v.uy_f = float(q[0]), float(q[1]), float(q[2])
+    var = p.get("variant", "II")
+    v.variant = VARIANT[var] if isinstance(var, str) else int(var)
+    return v
+
+
+def vn_amplification(params, kx, ky, want_G=False):
+    """Eigenvalues (nk, 9) complex, sorted by (-|lambda|, arg), and optionally
+    G (nk, 9, 9) complex, for one parameter set (dict with s, chi, qref,
+    variant, n, m)."""
+    L = load()
+    kx = np.ascontiguousarray(kx, dtype=np.float64).ravel()
+    ky = np.ascontiguousarray(ky, dtype=np.float64).ravel()
+    nk = kx.size
+    eig = np.empty((nk, 9, 2))
+    G = np.empty((nk, 9, 9, 2)) if want_G else None
+    v = _vn_params(params)
+    _check(L.vn_amplification(ctypes.byref(v), nk, kx.ctypes.data_as(_DP), ky.ctypes.data_as(_DP),
+                              eig.ctypes.data_as(_DP), G.ctypes.data_as(_DP) if want_G else None))
+    lam = eig[..., 0] + 1j * eig[..., 1]
+    if want_G:
+        return lam, G[..., 0] + 1j * G[..., 1]
+    return lam
+
+
+def vn_amplification_dev(param_list, kx, ky, eig, G=None, stream=None):
+    """Batched device form: kx, ky (nk,) float64 tensors; eig
+    (nparams, nk, 9, 2) float64 tensor; G optional (nparams, nk, 9, 9, 2)."""
+    arr = (lbm_vn_params * len(param_list))(*[_vn_params(p) for p in param_list])
+    _check(load().vn_amplification_dev(arr, len(param_list), int(kx.numel()), _dev(kx), _dev(ky),
+                                       _dev(eig), _dev(G), _stream_ptr(stream)))
+
+
+def lbm_device_copy(dst, src, nbytes, stream=None):
+    _check(load().lbm_device_copy(_dev(dst), _dev(src), int(nbytes), _stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------- convenience
+
+class Lattice:
+    """Owning wrapper of one lattice handle."""
+
+    def __init__(self, nx, ny, *, rho=None, ux=None, uy=None, **cfg_kw):
+        self.cfg = make_config(nx, ny, **cfg_kw)
+        self.h = lbm_create(self.cfg, rho, ux, uy)
+        self.nx, self.ny = int(nx), int(ny)
+
+    def set_sponge(self, chi=None, qref=None):
+        lbm_set_sponge(self.h, chi, qref)
+
+    def set_sponge_separable(self, chi_x=None, chi_y=None, combine="max", qref=None):
+        lbm_set_sponge_separable(self.h, chi_x, chi_y, combine, qref)
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+
+    def sync(self):
+        lbm_sync(self.h)
+
+    def moments(self):
+        return lbm_moments(self.h)
+
+    def diagnostics(self):
+        return lbm_diagnostics(self.h)
+
+    def populations(self):
+        return lbm_get_populations(self.h)
+
+    def set_populations(self, f):
+        lbm_set_populations(self.h, f)
+
+    def info(self):
+        return lbm_get_info(self.h)
+
+    def save_state(self):
+        return lbm_save_state(self.h)
+
+    def load_state(self, buf):
+        lbm_load_state(self.h, buf)
+
+    def close(self):
+        if self.h is not None:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

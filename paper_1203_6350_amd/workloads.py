@@ -82,8 +82,8 @@ def gaussian_pulses(nx: int, ny: int, centres, amps, halfwidths, rho0=1.0,
     Distances use the minimum image on the periodic lattice when ``periodic``.
     Returns (rho, ux, uy) as float64 [ny][nx].
     """
-    x = np.arange(nx, dtype=np.float64)[None, :]
-    y = np.arange(ny, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
     rho = np.full((ny, nx), float(rho0))
     for (cx, cy), a, b in zip(centres, amps, halfwidths):
         dx = x - cx
@@ -91,7 +91,10 @@ def gaussian_pulses(nx: int, ny: int, centres, amps, halfwidths, rho0=1.0,
         if periodic:
             dx = dx - nx * np.round(dx / nx)
             dy = dy - ny * np.round(dy / ny)
-        rho += a * np.exp(-math.log(2.0) * (dx * dx + dy * dy) / (b * b))
+        # exp(-ln2 (dx^2 + dy^2)/b^2) evaluated as an outer product
+        ex = np.exp(-math.log(2.0) * dx * dx / (b * b))
+        ey = np.exp(-math.log(2.0) * dy * dy / (b * b))
+        rho += a * np.outer(ey, ex)
     ux = np.full((ny, nx), float(u0[0]))
     uy = np.full((ny, nx), float(u0[1]))
     return rho, ux, uy

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/lbm.h declares, and rejects bad arguments before it
+touches a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1203_6350_amd import lbm, workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "lbm_create" in names and "vn_amplification" in names and len(names) >= 18
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    L = lbm.load()
+    for n in declared_functions():
+        assert hasattr(L, n)
+        if n not in ("lbm_destroy", "lbm_last_error"):
+            assert getattr(L, n).argtypes is not None, n
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(lbm.lbm_config) == 8 * 2 + 8 * 3 + 8 * 9 + 8 * 2 + 4 * 2 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm_vn_params) == 8 * 9 + 8 * 6 + 4 * 2
+    assert ctypes.sizeof(lbm.lbm_qref) == 24
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-1), dict(rho_base=0.0), dict(rho_base=float("nan")),
+    dict(s=(0, 0, 0, 2.5, 1.9, 1.9, 1.9, 1.9, 1.9)), dict(storage=7), dict(variant=9),
+    dict(storage="f16", f16_scale=0.0), dict(shift_n=-0.5), dict(nx=70000, ny=70000),
+])
+def test_create_rejects_bad_config(bad):
+    kw = dict(nx=8, ny=8)
+    kw.update(bad)
+    nx, ny = kw.pop("nx"), kw.pop("ny")
+    cfg = lbm.make_config(nx, ny, **kw)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(cfg)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert lbm.lbm_last_error()
+
+
+def test_required_bytes_is_host_only():
+    cfg = lbm.make_config(100, 30, storage="f32")
+    b = lbm.lbm_required_bytes(cfg)
+    # two lattices, nine planes, planes rounded to 256 bytes
+    plane = -(-100 * 30 * 4 // 256) * 256
+    assert b == 2 * 9 * plane
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = lbm.load()
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_sync(None) == lbm.LBM_EINVAL
+    L.lbm_destroy(None)  # accepted
+    out = np.empty(7)
+    assert L.lbm_diagnostics(None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lbm.LBM_EINVAL
+
+
+def test_vn_rejects_bad_parameters():
+    bad = dict(s=(1.9,) * 9, chi=-1.0, qref=(1, 0, 0), variant="II")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.vn_amplification(bad, np.zeros(4), np.zeros(4))
+    assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_sponge_generators():
+    """Workload generators: the quadratic ramp is chi_max at the edge cell and
+    zero from depth W; the normalised sigma~ of eq. normalizedsigma peaks at 1
+    at 4/5 of the layer and vanishes at both layer ends (Section 2.3)."""
+    r = wl.quadratic_ramp_1d(64, 10, 0.2)
+    assert r[0] == r[-1] == pytest.approx(0.2)
+    assert np.all(r[10:54] == 0)
+    assert np.all(np.diff(r[:11]) < 0)
+    W = 1000
+    s = wl.orszag_profile_1d(2 * W + 10, W, 1.0)
+    xi = wl.ramp_depth(2 * W + 10, W)
+    i = np.argmax(s[:W + 1])
+    assert s[i] == pytest.approx(1.0, abs=1e-5)
+    assert xi[i] == pytest.approx(0.8, abs=2e-3)
+    assert s[W] == 0.0
+    two = wl.sponge_2d(r, r)
+    assert two.shape == (64, 64) and two[0, 30] == pytest.approx(0.2) and two[30, 30] == 0
