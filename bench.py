@@ -62,6 +62,7 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
                       f16_scale=5e-4, stream=stream)
     cx, cy = spec.chi_1d()
     lat.set_sponge_separable(cx, cy, "max", spec.qref)
+    tuning, tune_ms = lat.autotune(reps=10)
     diag = torch.empty(7, dtype=torch.float64, device="cuda")
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -90,7 +91,7 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
     cells = spec.nx * spec.ny
     return dict(wall_s=wall, ms_per_step=1e3 * wall / steps,
                 mlups=cells * steps / wall / 1e6,
-                kernel_ms=sum(durs) / len(durs), diag=[float(x) for x in d])
+                kernel_ms=sum(durs) / len(durs), diag=[float(x) for x in d], tuning=tuning)
 
 
 def copy_bandwidth(lbm, torch, nbytes=2 << 30, reps=20):
@@ -198,7 +199,8 @@ def main():
                      "kernel_ms": r["kernel_ms"]},
         "per_variant": {v: {"mlups": x["mlups"], "kernel_ms": x["kernel_ms"],
                             "achieved_gbps": bytes_per_cell * cells / (x["kernel_ms"] * 1e-3) / 1e9,
-                            "nonfinite_cells": x["diag"][6], "max_dev": x["diag"][5]}
+                            "nonfinite_cells": x["diag"][6], "max_dev": x["diag"][5],
+                            "tuning": x["tuning"]}
                         for v, x in results.items()},
         "copy_kernel_gbps": copy_gbps,
     }

@@ -48,7 +48,8 @@ extern "C" {
  * w_i rho_base). */
 #define LBM_STORAGE_F64 0 /* FP64 storage, FP64 arithmetic                */
 #define LBM_STORAGE_F32 1 /* FP32 storage, FP32 arithmetic                */
-#define LBM_STORAGE_F16 2 /* FP16 storage of g_i / (w_i f16_scale), FP32 arithmetic */
+#define LBM_STORAGE_F16 2 /* FP16 storage of g_i / 2^e_i with 2^e_i the power
+                             of two nearest to w_i f16_scale, FP32 arithmetic */
 
 /* ---- damping variants (Section 2.2, Gamma = chi I, eq. eq:gamma) ------ */
 #define LBM_VARIANT_NONE 0 /* plain scheme, eq. blbs                       */
@@ -176,6 +177,27 @@ int lbm_save_state(lbm_handle *h, void *host, size_t bytes);
 int lbm_load_state(lbm_handle *h, const void *host, size_t bytes);
 
 int lbm_get_info(lbm_handle *h, lbm_info *info);
+
+/* ---- kernel tuning ----------------------------------------------------
+ * Launch shape of the step kernel. Every choice computes the same per-cell
+ * arithmetic, so results are bit-identical across tunings. */
+typedef struct lbm_tuning {
+  int32_t kernel;      /* 0: one cell per thread; 1: 16-byte vector rows
+                          (4 cells FP32, 2 FP64, 8 FP16; needs nx % cells == 0,
+                          otherwise the library falls back to 0)            */
+  int32_t block;       /* threads per block: 64, 128, 256 or 512            */
+  int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
+  int32_t pad_;
+} lbm_tuning;
+
+int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t);
+int lbm_get_tuning(lbm_handle *h, lbm_tuning *t);
+
+/* Time every candidate launch shape on the handle's own lattice (reps
+ * launches each, after two warm-up launches; the state is not advanced),
+ * keep the fastest and return it with its mean launch time in ms.
+ * best and best_ms may be NULL. Synchronises. */
+int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms);
 
 /* Release all resources of the handle; NULL is accepted. */
 void lbm_destroy(lbm_handle *h);

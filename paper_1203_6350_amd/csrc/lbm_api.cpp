@@ -225,7 +225,9 @@ int create_common(const lbm_config *cfg, const double *rho, const double *ux,
   h->cfg.pitch = pitch;
   h->cfg.plane_stride = ps;
   h->cfg.chi_mode = lbm::CHI_ZERO;
-  h->cfg.tile = 0;
+  h->cfg.kernel = lbm::KERNEL_VEC;
+  h->cfg.block = 256;
+  h->cfg.nontemporal = 0;
   if (buf_a) {
     if (!buf_b || bytes_each < h->lat_bytes || ((uintptr_t)buf_a & 255) ||
         ((uintptr_t)buf_b & 255)) {
@@ -242,6 +244,14 @@ int create_common(const lbm_config *cfg, const double *rho, const double *ux,
         lbm_destroy(h);
         return hip_fail(e, "hipMalloc(lattice)");
       }
+    }
+  }
+  // zero both lattices so that plane padding is deterministic
+  for (int k = 0; k < 2; ++k) {
+    hipError_t ez = hipMemsetAsync(h->lat[k], 0, h->lat_bytes, h->stream);
+    if (ez != hipSuccess) {
+      lbm_destroy(h);
+      return hip_fail(ez, "hipMemset(lattice)");
     }
   }
   hipError_t e = hipMalloc((void **)&h->diag_partials, lbm::diag_partials_bytes(h->cfg));
@@ -469,6 +479,79 @@ int lbm_get_info(lbm_handle *h, lbm_info *info) {
   info->elem_bytes = lbm::elem_bytes_of(h->user.storage);
   info->chi_mode = h->cfg.chi_mode;
   info->device_bytes = 2 * h->lat_bytes;
+  return LBM_OK;
+}
+
+int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t) {
+  if (!h || !t) return fail(LBM_EINVAL, "NULL argument");
+  if (t->kernel != 0 && t->kernel != 1) return fail(LBM_EINVAL, "kernel must be 0 or 1");
+  if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
+    return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512");
+  if (t->nontemporal != 0 && t->nontemporal != 1) return fail(LBM_EINVAL, "nontemporal must be 0 or 1");
+  h->cfg.kernel = t->kernel;
+  h->cfg.block = t->block;
+  h->cfg.nontemporal = t->nontemporal;
+  return LBM_OK;
+}
+
+int lbm_get_tuning(lbm_handle *h, lbm_tuning *t) {
+  if (!h || !t) return fail(LBM_EINVAL, "NULL argument");
+  t->kernel = h->cfg.kernel == lbm::KERNEL_VEC && lbm::vec_supported(h->cfg) ? 1 : 0;
+  t->block = h->cfg.block;
+  t->nontemporal = t->kernel ? h->cfg.nontemporal : 0;
+  t->pad_ = 0;
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+  std::vector<lbm_tuning> cands;
+  const int blocks[4] = {64, 128, 256, 512};
+  for (int b : blocks) cands.push_back(lbm_tuning{0, b, 0, 0});
+  if (lbm::vec_supported(h->cfg))
+    for (int nt = 0; nt < 2; ++nt)
+      for (int b : blocks) cands.push_back(lbm_tuning{1, b, nt, 0});
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  const lbm::StepConfig saved = h->cfg;
+  double best_t = 1e300;
+  lbm_tuning best_c = cands[0];
+  for (const lbm_tuning &c : cands) {
+    h->cfg.kernel = c.kernel;
+    h->cfg.block = c.block;
+    h->cfg.nontemporal = c.nontemporal;
+    // the candidate reads the current lattice and overwrites the other one,
+    // whose contents the next step replaces anyway
+    for (int k = 0; k < 2 + reps && e == hipSuccess; ++k) {
+      if (k == 2) e = hipEventRecord(e0, h->stream);
+      if (e == hipSuccess) e = lbm::launch_step(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    const double per = ms / reps;
+    if (per < best_t) {
+      best_t = per;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->cfg = saved;
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  h->cfg.kernel = best_c.kernel;
+  h->cfg.block = best_c.block;
+  h->cfg.nontemporal = best_c.nontemporal;
+  if (best) *best = best_c;
+  if (best_ms) *best_ms = best_t;
   return LBM_OK;
 }
 

@@ -25,8 +25,15 @@ struct StepConfig {
   const void *chi_field; // [ny][pitch] compute type, CHI_FIELD
   const void *chi_x;     // [nx] compute type
   const void *chi_y;     // [ny] compute type
-  int tile;              // kernel variant chosen by the tuner (0 = generic)
+  int kernel;            // KERNEL_GENERIC or KERNEL_VEC
+  int block;             // threads per block: 64, 128, 256 or 512
+  int nontemporal;       // 1: streaming (non-temporal) stores (vector kernel)
 };
+
+enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1 };
+bool vec_supported(const StepConfig &c);
+// FP16 mode: stored value = deviation / storage_scale (a power of two).
+double storage_scale(const StepConfig &c, int i);
 
 // Launchers (lbm_kernels.hip). All enqueue on `stream` and return the HIP
 // status of the launch.

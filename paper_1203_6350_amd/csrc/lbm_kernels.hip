@@ -9,10 +9,21 @@
 // element is read once and written once per step, the writes are fully
 // coalesced and the reads of the six x-shifted planes are offset by one
 // element.
+#include <cmath>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
 namespace lbm {
+
+// Per-direction scale of the FP16 mode: the power of two nearest to
+// w_i * f16_scale. A power of two makes the scaling exact, so the stored half
+// is the single rounding of the FP32 deviation whichever instruction sequence
+// the compiler picks for scale-and-convert.
+double storage_scale(const StepConfig &c, int i) {
+  if (c.storage != 2) return 1.0;
+  return std::exp2(std::nearbyint(std::log2(w_of(i) * c.f16_scale)));
+}
 
 template <typename S>
 struct Lat {
@@ -31,7 +42,7 @@ static Lat<S> make_lat(const StepConfig &c) {
   L.pitch = c.pitch;
   L.ps = c.plane_stride;
   for (int i = 0; i < 9; ++i) {
-    const double sc = c.storage == 2 ? w_of(i) * c.f16_scale : 1.0;
+    const double sc = storage_scale(c, i);
     L.scale[i] = C(sc);
     L.inv_scale[i] = C(1.0 / sc);
   }
@@ -98,18 +109,159 @@ __global__ __launch_bounds__(BX) void step_generic(
     Store<S>::store(dst + i * ps + r0 + x, g[i], L.inv_scale[i]);
 }
 
-template <typename S, int VAR, int CHI>
-static hipError_t launch_step_t(const StepConfig &c, const void *src,
-                                void *dst, hipStream_t stream) {
+// Vector kernel: each thread owns V = 16 / sizeof(S) consecutive cells of one
+// row and moves every plane with one 16-byte load and one 16-byte store. The
+// three planes with c_x = 0 are read aligned; the six x-shifted planes are
+// read one element to the left or right (element-aligned 16-byte loads, which
+// the HSA unaligned access mode serves). The first and last thread of a row
+// take the periodic wrap with element loads. Requires nx % V == 0.
+template <typename S>
+struct Vec16 {
+  S v[16 / sizeof(S)];
+};
+
+template <typename S>
+__device__ __forceinline__ void load16(Vec16<S> &d, const S *p) {
+  __builtin_memcpy(&d, p, 16);
+}
+
+template <bool NT, typename S>
+__device__ __forceinline__ void store16(S *p, const Vec16<S> &d) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 w;
+  __builtin_memcpy(&w, &d, 16);
+  if (NT)
+    __builtin_nontemporal_store(w, (u4 *)p);
+  else
+    *(u4 *)p = w;
+}
+
+template <typename S, int VAR, int CHI, int BX, bool NT>
+__global__ __launch_bounds__(BX) void step_vec(
+    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
+    CollideParams<typename Store<S>::C> p,
+    const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix,
+    const typename Store<S>::C *__restrict__ chiy) {
+  typedef typename Store<S>::C C;
+  constexpr int V = 16 / sizeof(S);
+  const int vpr = L.nx / V;
+  const int bpr = (vpr + BX - 1) / BX;
+  const int y = blockIdx.x / bpr;
+  const int xv = (blockIdx.x - y * bpr) * BX + threadIdx.x;
+  if (xv >= vpr) return;
+  const int x0 = xv * V;
+  const int ym = y == 0 ? L.ny - 1 : y - 1;
+  const int yp = y == L.ny - 1 ? 0 : y + 1;
+  const int64_t r0 = (int64_t)y * L.pitch, rm = (int64_t)ym * L.pitch,
+                rp = (int64_t)yp * L.pitch;
+  const int64_t ps = L.ps;
+  Vec16<S> in[9];
+  // c_x = 0: aligned
+  load16(in[0], src + 0 * ps + r0 + x0);
+  load16(in[2], src + 2 * ps + rm + x0);
+  load16(in[4], src + 4 * ps + rp + x0);
+  // c_x = +1 (1, 5, 8) pull from x - 1; c_x = -1 (3, 6, 7) pull from x + 1
+  if (x0 > 0) {
+    load16(in[1], src + 1 * ps + r0 + x0 - 1);
+    load16(in[5], src + 5 * ps + rm + x0 - 1);
+    load16(in[8], src + 8 * ps + rp + x0 - 1);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int xs = v == 0 ? L.nx - 1 : v - 1;
+      in[1].v[v] = src[1 * ps + r0 + xs];
+      in[5].v[v] = src[5 * ps + rm + xs];
+      in[8].v[v] = src[8 * ps + rp + xs];
+    }
+  }
+  if (x0 + V < L.nx) {
+    load16(in[3], src + 3 * ps + r0 + x0 + 1);
+    load16(in[6], src + 6 * ps + rm + x0 + 1);
+    load16(in[7], src + 7 * ps + rp + x0 + 1);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int xs = x0 + v + 1 == L.nx ? 0 : x0 + v + 1;
+      in[3].v[v] = src[3 * ps + r0 + xs];
+      in[6].v[v] = src[6 * ps + rm + xs];
+      in[7].v[v] = src[7 * ps + rp + xs];
+    }
+  }
+  Vec16<S> out[9];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    C g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = Store<S>::load(&in[i].v[v], L.scale[i]);
+    const C chi = chi_at<C, CHI>(chi_field, chix, chiy, r0 + x0 + v, x0 + v, y);
+    collide<C, VAR>(g, chi, p);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Store<S>::store(&out[i].v[v], g[i], L.inv_scale[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) store16<NT>(dst + i * ps + r0 + x0, out[i]);
+}
+
+template <typename S, int VAR, int CHI, int BX>
+static hipError_t launch_generic(const StepConfig &c, const void *src, void *dst,
+                                 hipStream_t stream) {
   typedef typename Store<S>::C C;
   Lat<S> L = make_lat<S>(c);
   CollideParams<C> p = make_params<C>(c);
-  constexpr int BX = 256;
   const int64_t blocks = (int64_t)((c.nx + BX - 1) / BX) * c.ny;
   step_generic<S, VAR, CHI, BX><<<dim3((unsigned)blocks), dim3(BX), 0, stream>>>(
       (const S *)src, (S *)dst, L, p, (const C *)c.chi_field,
       (const C *)c.chi_x, (const C *)c.chi_y);
   return hipGetLastError();
+}
+
+template <typename S, int VAR, int CHI, int BX, bool NT>
+static hipError_t launch_vec(const StepConfig &c, const void *src, void *dst,
+                             hipStream_t stream) {
+  typedef typename Store<S>::C C;
+  constexpr int V = 16 / sizeof(S);
+  Lat<S> L = make_lat<S>(c);
+  CollideParams<C> p = make_params<C>(c);
+  const int vpr = c.nx / V;
+  const int64_t blocks = (int64_t)((vpr + BX - 1) / BX) * c.ny;
+  step_vec<S, VAR, CHI, BX, NT><<<dim3((unsigned)blocks), dim3(BX), 0, stream>>>(
+      (const S *)src, (S *)dst, L, p, (const C *)c.chi_field,
+      (const C *)c.chi_x, (const C *)c.chi_y);
+  return hipGetLastError();
+}
+
+bool vec_supported(const StepConfig &c) {
+  const int V = 16 / elem_bytes_of(c.storage);
+  return c.nx % V == 0 && c.nx >= V && c.pitch % V == 0;
+}
+
+template <typename S, int VAR, int CHI>
+static hipError_t launch_step_t(const StepConfig &c, const void *src,
+                                void *dst, hipStream_t stream) {
+  const int kernel = c.kernel == KERNEL_VEC && vec_supported(c) ? KERNEL_VEC : KERNEL_GENERIC;
+  if (kernel == KERNEL_GENERIC) {
+    switch (c.block) {
+      case 64: return launch_generic<S, VAR, CHI, 64>(c, src, dst, stream);
+      case 128: return launch_generic<S, VAR, CHI, 128>(c, src, dst, stream);
+      case 512: return launch_generic<S, VAR, CHI, 512>(c, src, dst, stream);
+      default: return launch_generic<S, VAR, CHI, 256>(c, src, dst, stream);
+    }
+  }
+  if (c.nontemporal) {
+    switch (c.block) {
+      case 64: return launch_vec<S, VAR, CHI, 64, true>(c, src, dst, stream);
+      case 128: return launch_vec<S, VAR, CHI, 128, true>(c, src, dst, stream);
+      case 512: return launch_vec<S, VAR, CHI, 512, true>(c, src, dst, stream);
+      default: return launch_vec<S, VAR, CHI, 256, true>(c, src, dst, stream);
+    }
+  }
+  switch (c.block) {
+    case 64: return launch_vec<S, VAR, CHI, 64, false>(c, src, dst, stream);
+    case 128: return launch_vec<S, VAR, CHI, 128, false>(c, src, dst, stream);
+    case 512: return launch_vec<S, VAR, CHI, 512, false>(c, src, dst, stream);
+    default: return launch_vec<S, VAR, CHI, 256, false>(c, src, dst, stream);
+  }
 }
 
 template <typename S, int VAR>
@@ -225,7 +377,7 @@ static DevLat make_devlat(const StepConfig &c) {
   d.ubx = c.ubx;
   d.uby = c.uby;
   for (int i = 0; i < 9; ++i) {
-    d.scale[i] = c.storage == 2 ? w_of(i) * c.f16_scale : 1.0;
+    d.scale[i] = storage_scale(c, i);
     d.inv_scale[i] = 1.0 / d.scale[i];
   }
   return d;
@@ -474,20 +626,27 @@ hipError_t launch_diagnostics(const StepConfig &c, const void *src,
 }
 
 // ---------------------------------------------------------------- copy probe
-__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src,
-                                                   float4 *__restrict__ dst,
+// One 16-byte element per thread, exact grid, non-temporal stores: the plain
+// streaming copy used to calibrate bandwidth and traffic counters.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src,
+                                                   uint4 *__restrict__ dst,
                                                    int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    dst[i] = src[i];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 w;
+    __builtin_memcpy(&w, &src[i], 16);
+    __builtin_nontemporal_store(w, (u4 *)&dst[i]);
+  }
 }
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,
                        hipStream_t stream) {
   const int64_t n = (int64_t)(bytes / 16);
-  const int64_t want = (n + 255) / 256;
-  const unsigned blocks = (unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536);
-  copy_kernel<<<blocks, 256, 0, stream>>>((const float4 *)src, (float4 *)dst, n);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  copy_kernel<<<dim3((unsigned)blocks), 256, 0, stream>>>((const uint4 *)src, (uint4 *)dst, n);
   return hipGetLastError();
 }
 

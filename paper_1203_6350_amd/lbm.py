@@ -49,6 +49,14 @@ class lbm_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t)]
 
 
+class lbm_tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"kernel": self.kernel, "block": self.block, "nontemporal": self.nontemporal}
+
+
 class lbm_vn_params(ctypes.Structure):
     _fields_ = [("s", ctypes.c_double * 9), ("shift_n", ctypes.c_double),
                 ("shift_m", ctypes.c_double), ("chi", ctypes.c_double),
@@ -92,6 +100,9 @@ def load(path: str | None = None):
         "lbm_get_populations": [_H, _DP],
         "lbm_set_populations": [_H, _DP],
         "lbm_get_info": [_H, ctypes.POINTER(lbm_info)],
+        "lbm_set_tuning": [_H, ctypes.POINTER(lbm_tuning)],
+        "lbm_get_tuning": [_H, ctypes.POINTER(lbm_tuning)],
+        "lbm_autotune": [_H, i32, ctypes.POINTER(lbm_tuning), _DP],
         "lbm_state_bytes": [_H, ctypes.POINTER(sz)],
         "lbm_save_state": [_H, vp, sz],
         "lbm_load_state": [_H, vp, sz],
@@ -261,6 +272,24 @@ def lbm_set_populations(h, f):
     _check(load().lbm_set_populations(h, pa))
 
 
+def lbm_set_tuning(h, kernel=1, block=256, nontemporal=0):
+    t = lbm_tuning(int(kernel), int(block), int(nontemporal), 0)
+    _check(load().lbm_set_tuning(h, ctypes.byref(t)))
+
+
+def lbm_get_tuning(h):
+    t = lbm_tuning()
+    _check(load().lbm_get_tuning(h, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def lbm_autotune(h, reps=10):
+    t = lbm_tuning()
+    ms = ctypes.c_double()
+    _check(load().lbm_autotune(h, int(reps), ctypes.byref(t), ctypes.byref(ms)))
+    return t.as_dict(), ms.value
+
+
 def lbm_state_bytes(h):
     b = ctypes.c_size_t()
     _check(load().lbm_state_bytes(h, ctypes.byref(b)))
@@ -369,6 +398,15 @@ class Lattice:
 
     def info(self):
         return lbm_get_info(self.h)
+
+    def set_tuning(self, **kw):
+        lbm_set_tuning(self.h, **kw)
+
+    def tuning(self):
+        return lbm_get_tuning(self.h)
+
+    def autotune(self, reps=10):
+        return lbm_autotune(self.h, reps)
 
     def save_state(self):
         return lbm_save_state(self.h)

