@@ -112,6 +112,95 @@ def copy_bandwidth(lbm, torch, nbytes=2 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def make_domain(lbm, spec, stream):
+    rho, ux, uy = spec.fields()
+    lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage=spec.storage,
+                      variant=spec.variant, s=spec.s, ux_base=spec.base_state[1], stream=stream)
+    cx, cy = spec.chi_1d()
+    lat.set_sponge_separable(cx, cy, "max", spec.qref)
+    return lat
+
+
+def batched_leg(lbm, wl, torch, steps=1000, vn_sets=64, vn_nk=256):
+    """256 uneven domains: one persistent launch per step (graph-captured)
+    against plain per-domain launches; plus the Von Neumann sweep."""
+    specs = wl.batch_c4()
+    cells = sum(sp.nx * sp.ny for sp in specs)
+    s = torch.cuda.current_stream()
+    # plain: one launch per domain per step, all queued on one stream
+    plain = [make_domain(lbm, sp, s) for sp in specs]
+    for lat in plain:
+        lat.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in plain:
+        lat.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # batched: the same domains, same number of steps
+    lats = [make_domain(lbm, sp, s) for sp in specs]
+    b = lbm.Batch(lats)
+    b.step(2)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    # Type I members with s + chi > 2 blow up by design (non-finite state);
+    # the finite members are compared bit for bit
+    same, unstable = True, 0
+    for p_, q_ in zip(plain, lats):
+        dp_ = p_.diagnostics()
+        if dp_[6] > 0:
+            unstable += 1
+            continue
+        same = same and bool((p_.save_state() == q_.save_state()).all())
+    b.close()
+    for lat in plain + lats:
+        lat.close()
+    # Von Neumann sweep: vn_sets parameter sets on a vn_nk^2 wavenumber grid
+    kx, ky = wl.vn_grid(vn_nk)
+    dkx = torch.from_numpy(kx).cuda()
+    dky = torch.from_numpy(ky).cuda()
+    params = wl.vn_param_sets(vn_sets)
+    eig = torch.empty((vn_sets, kx.size, 9, 2), dtype=torch.float64, device="cuda")
+    lbm.vn_amplification_dev(params[:2], dkx, dky, eig[:2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm.vn_amplification_dev(params, dkx, dky, eig)
+    torch.cuda.synchronize()
+    t_vn = time.perf_counter() - t0
+    finite = bool(torch.isfinite(eig).all().item())
+    return {"domains": len(specs), "cells": cells, "steps": steps,
+            "batched_mlups": cells * steps / t_batch / 1e6,
+            "plain_mlups": cells * steps / t_plain / 1e6,
+            "speedup": t_plain / t_batch, "bitwise_equal_finite_members": same,
+            "unstable_members": unstable,
+            "vn_sets": vn_sets, "vn_kpoints": int(kx.size) * vn_sets,
+            "vn_kpoints_per_s": kx.size * vn_sets / t_vn, "vn_seconds": t_vn,
+            "vn_all_finite": finite}
+
+
+def serving_leg(torch, rates=(50, 100, 200, 500), count=2000, warmup=200, budget_gb=200):
+    """Open-loop Poisson arrivals of domain and Von Neumann requests; latency
+    from arrival to result on the host."""
+    from paper_1203_6350_amd import serve
+    out = {}
+    for rate in rates:
+        print("bench: serving at %d req/s, %d requests" % (rate, count), file=sys.stderr, flush=True)
+        reqs = serve.make_requests(float(rate), count, seed=rate)
+        ex = serve.GpuExecutor()
+        srv = serve.Server(ex, budget_bytes=int(budget_gb * (1 << 30)))
+        st = srv.run(reqs)
+        ex.close()
+        summ = st.summary(reqs, warmup=warmup)
+        summ["offered_mlups"] = sum(r.steps * r.spec.nx * r.spec.ny for r in reqs
+                                    if r.kind == "domain") / reqs[-1].arrival / 1e6
+        out[str(rate)] = summ
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(spec, fields, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -140,6 +229,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -206,6 +298,12 @@ def main():
     }
     if copy_gbps:
         out["roofline"]["frac_of_copy"] = achieved / copy_gbps
+    if not args.no_batch:
+        print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(lbm, wl, torch)
+    if not args.no_serve:
+        out["served"] = serving_leg(torch, count=args.serve_requests,
+                                    warmup=args.serve_requests // 10)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, fields, args.cpu_steps)

@@ -104,6 +104,13 @@ typedef struct lbm_handle lbm_handle;
 int lbm_create(const lbm_config *cfg, const double *rho, const double *ux,
                const double *uy, lbm_handle **out);
 
+/* Re-initialise to f = f^eq(rho, u) from device FP64 fields [ny][nx], each
+ * of which may be NULL for the base value (rho_base, ux_base, uy_base).
+ * Asynchronous on the handle's stream; the fields are not validated and must
+ * stay valid until the work completes. Resets steps_done to 0. */
+int lbm_init_fields_dev(lbm_handle *h, const double *rho, const double *ux,
+                        const double *uy);
+
 /* Bytes of device memory one lattice pair needs (both lattices, padded). */
 int lbm_required_bytes(const lbm_config *cfg, size_t *bytes);
 
@@ -203,6 +210,43 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
 void lbm_destroy(lbm_handle *h);
 
 const char *lbm_last_error(void);
+
+/* ---- batched stepping of many lattices --------------------------------
+ * A batch steps many independent lattices (each an lbm_handle with its own
+ * size, relaxation rates, damping variant, sponge and reference state) with
+ * one persistent launch per time step, captured in HIP graphs. All members
+ * must share the storage mode and the device. Each member's result is
+ * bit-identical to stepping it alone with lbm_step.
+ * While a batch has work in flight its members must not be used on their
+ * own; lbm_batch_sync makes them usable again. Member parameters (sponge,
+ * q_ref, tuning) are read at every tick, so they may change between ticks.
+ * The batch keeps pointers to the members: destroy the batch before them. */
+typedef struct lbm_batch lbm_batch;
+
+/* members: count >= 1 distinct handles; stream: hipStream_t for the batch
+ * (NULL: the batch creates its own stream). */
+int lbm_batch_create(lbm_handle *const *members, int32_t count, void *stream,
+                     lbm_batch **out);
+
+/* Advance every member by n >= 0 steps (enqueued; returns without waiting). */
+int lbm_batch_step(lbm_batch *b, int64_t n);
+
+/* One tick of `tick` >= 1 launches in which member i takes member_steps[i]
+ * steps (0 <= member_steps[i] <= tick; NULL means tick for all). Members
+ * that finish early keep their state for the rest of the tick. */
+int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps);
+
+/* Replace the member list (same rules as lbm_batch_create). The tile table
+ * is rewritten in place when it fits, so graphs captured earlier stay valid.
+ * Synchronises the batch stream. */
+int lbm_batch_set_members(lbm_batch *b, lbm_handle *const *members,
+                          int32_t count);
+
+/* Persistent workgroups per compute unit (1..64, default 8). */
+int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu);
+
+int lbm_batch_sync(lbm_batch *b);
+void lbm_batch_destroy(lbm_batch *b);
 
 /* ---- Von Neumann analysis (Section 3.2, eqs. eq:linearized, sec:matrix) --
  * For the scheme linearised about f^eq(q_ref) with uniform chi, computes per

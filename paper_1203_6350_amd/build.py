@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip"]
+SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip", "lbm_batch.hip"]
 
 # - no automatic FMA contraction: the kernels place their fused multiply-adds
 #   explicitly, so every launch shape gives the same bits;

@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -137,7 +139,7 @@ void fill_cfg(lbm_handle *h) {
 int upload_compute(lbm_handle *h, const double *src, size_t n, void **dst) {
   const bool f64 = h->user.storage == LBM_STORAGE_F64;
   const size_t eb = f64 ? 8 : 4;
-  if (!*dst) HIP_TRY(hipMalloc(dst, n * eb), "hipMalloc(sponge)");
+  if (!*dst) HIP_TRY(hipMallocAsync(dst, n * eb, h->stream), "hipMallocAsync(sponge)");
   std::vector<float> tmp;
   const void *p = src;
   if (!f64) {
@@ -151,11 +153,23 @@ int upload_compute(lbm_handle *h, const double *src, size_t n, void **dst) {
   return LBM_OK;
 }
 
+// Auxiliary buffers (sponge arrays, staging, diagnostics) use stream-ordered
+// allocation on the handle's stream, so creating and destroying handles
+// never waits for the whole device.
 void free_sponge(lbm_handle *h) {
-  if (h->chi_field) (void)hipFree(h->chi_field);
-  if (h->chi_x) (void)hipFree(h->chi_x);
-  if (h->chi_y) (void)hipFree(h->chi_y);
+  if (h->chi_field) (void)hipFreeAsync(h->chi_field, h->stream);
+  if (h->chi_x) (void)hipFreeAsync(h->chi_x, h->stream);
+  if (h->chi_y) (void)hipFreeAsync(h->chi_y, h->stream);
   h->chi_field = h->chi_x = h->chi_y = nullptr;
+}
+
+int ensure_diag(lbm_handle *h) {
+  if (h->diag_partials) return LBM_OK;
+  HIP_TRY(hipMallocAsync((void **)&h->diag_partials, lbm::diag_partials_bytes(h->cfg), h->stream),
+          "hipMallocAsync(diagnostics)");
+  HIP_TRY(hipMallocAsync((void **)&h->diag_out, 8 * sizeof(double), h->stream),
+          "hipMallocAsync(diagnostics)");
+  return LBM_OK;
 }
 
 int check_qref(const lbm_qref *q) {
@@ -181,23 +195,24 @@ int init_state(lbm_handle *h, const double *rho, const double *ux,
     for (int64_t i = 0; i < N; ++i)
       if (!(rho[i] > 0) || !is_fin(rho[i]) || (ux && !is_fin(ux[i])) || (uy && !is_fin(uy[i])))
         return fail(LBM_EINVAL, "initial fields must be finite with rho > 0");
-    HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 3 * N), "hipMalloc(init)");
+    HIP_TRY(hipMallocAsync((void **)&d, sizeof(double) * 3 * N, h->stream), "hipMallocAsync(init)");
     std::vector<double> zero;
     if (!ux || !uy) zero.assign(N, 0.0);
-    hipError_t e = hipMemcpy(d, rho, sizeof(double) * N, hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpyAsync(d, rho, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
-      e = hipMemcpy(d + N, ux ? ux : zero.data(), sizeof(double) * N, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(d + N, ux ? ux : zero.data(), sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
-      e = hipMemcpy(d + 2 * N, uy ? uy : zero.data(), sizeof(double) * N, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(d + 2 * N, uy ? uy : zero.data(), sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) {
-      (void)hipFree(d);
+      (void)hipFreeAsync(d, h->stream);
       return hip_fail(e, "hipMemcpy(init)");
     }
   }
   hipError_t e = lbm::launch_init(h->cfg, d, d ? d + N : nullptr, d ? d + 2 * N : nullptr,
                                   h->lat[0], h->stream);
+  if (d) (void)hipFreeAsync(d, h->stream);
+  // the host arrays (and the zero vector) must outlive the copies
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (d) (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "init kernel");
   h->cur = 0;
   h->steps = 0;
@@ -253,12 +268,6 @@ int create_common(const lbm_config *cfg, const double *rho, const double *ux,
       lbm_destroy(h);
       return hip_fail(ez, "hipMemset(lattice)");
     }
-  }
-  hipError_t e = hipMalloc((void **)&h->diag_partials, lbm::diag_partials_bytes(h->cfg));
-  if (e == hipSuccess) e = hipMalloc((void **)&h->diag_out, 8 * sizeof(double));
-  if (e != hipSuccess) {
-    lbm_destroy(h);
-    return hip_fail(e, "hipMalloc(diagnostics)");
   }
   fill_cfg(h);
   rc = init_state(h, rho, ux, uy);
@@ -381,19 +390,21 @@ int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   const int64_t N = h->user.nx * h->user.ny;
   double *d = nullptr;
-  HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 3 * N), "hipMalloc(moments)");
+  HIP_TRY(hipMallocAsync((void **)&d, sizeof(double) * 3 * N, h->stream), "hipMallocAsync(moments)");
   hipError_t e = lbm::launch_moments(h->cfg, h->lat[h->cur], d, d + N, d + 2 * N, h->stream);
+  if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && ux) e = hipMemcpyAsync(ux, d + N, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && uy) e = hipMemcpyAsync(uy, d + 2 * N, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+  (void)hipFreeAsync(d, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e == hipSuccess && rho) e = hipMemcpy(rho, d, sizeof(double) * N, hipMemcpyDeviceToHost);
-  if (e == hipSuccess && ux) e = hipMemcpy(ux, d + N, sizeof(double) * N, hipMemcpyDeviceToHost);
-  if (e == hipSuccess && uy) e = hipMemcpy(uy, d + 2 * N, sizeof(double) * N, hipMemcpyDeviceToHost);
-  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "moments");
   return LBM_OK;
 }
 
 int lbm_diagnostics(lbm_handle *h, double out[7]) {
   if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+  int rc = ensure_diag(h);
+  if (rc) return rc;
   hipError_t e = lbm::launch_diagnostics(h->cfg, h->lat[h->cur], h->diag_partials,
                                          h->diag_out, h->stream);
   if (e == hipSuccess)
@@ -405,6 +416,8 @@ int lbm_diagnostics(lbm_handle *h, double out[7]) {
 
 int lbm_diagnostics_dev(lbm_handle *h, double *out7_dev) {
   if (!h || !out7_dev) return fail(LBM_EINVAL, "NULL argument");
+  int rc = ensure_diag(h);
+  if (rc) return rc;
   hipError_t e = lbm::launch_diagnostics(h->cfg, h->lat[h->cur], h->diag_partials,
                                          out7_dev, h->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
@@ -415,11 +428,11 @@ int lbm_get_populations(lbm_handle *h, double *f) {
   if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
   const int64_t N = h->user.nx * h->user.ny;
   double *d = nullptr;
-  HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 9 * N), "hipMalloc(populations)");
+  HIP_TRY(hipMallocAsync((void **)&d, sizeof(double) * 9 * N, h->stream), "hipMallocAsync(populations)");
   hipError_t e = lbm::launch_get_populations(h->cfg, h->lat[h->cur], d, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f, d, sizeof(double) * 9 * N, hipMemcpyDeviceToHost, h->stream);
+  (void)hipFreeAsync(d, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e == hipSuccess) e = hipMemcpy(f, d, sizeof(double) * 9 * N, hipMemcpyDeviceToHost);
-  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "get_populations");
   return LBM_OK;
 }
@@ -430,12 +443,11 @@ int lbm_set_populations(lbm_handle *h, const double *f) {
   for (int64_t i = 0; i < 9 * N; ++i)
     if (!is_fin(f[i])) return fail(LBM_EINVAL, "populations must be finite");
   double *d = nullptr;
-  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-  HIP_TRY(hipMalloc((void **)&d, sizeof(double) * 9 * N), "hipMalloc(populations)");
-  hipError_t e = hipMemcpy(d, f, sizeof(double) * 9 * N, hipMemcpyHostToDevice);
+  HIP_TRY(hipMallocAsync((void **)&d, sizeof(double) * 9 * N, h->stream), "hipMallocAsync(populations)");
+  hipError_t e = hipMemcpyAsync(d, f, sizeof(double) * 9 * N, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = lbm::launch_set_populations(h->cfg, d, h->lat[0], h->stream);
+  (void)hipFreeAsync(d, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "set_populations");
   h->cur = 0;
   h->steps = 0;
@@ -557,18 +569,295 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
 
 void lbm_destroy(lbm_handle *h) {
   if (!h) return;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
-  else (void)hipDeviceSynchronize();
-  if (h->own_lat)
+  free_sponge(h);
+  if (h->diag_partials) (void)hipFreeAsync(h->diag_partials, h->stream);
+  if (h->diag_out) (void)hipFreeAsync(h->diag_out, h->stream);
+  if (h->own_lat) {
+    (void)hipStreamSynchronize(h->stream);
     for (int k = 0; k < 2; ++k)
       if (h->lat[k]) (void)hipFree(h->lat[k]);
-  free_sponge(h);
-  if (h->diag_partials) (void)hipFree(h->diag_partials);
-  if (h->diag_out) (void)hipFree(h->diag_out);
+  }
   delete h;
 }
 
+int lbm_init_fields_dev(lbm_handle *h, const double *rho, const double *ux,
+                        const double *uy) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  hipError_t e = lbm::launch_init(h->cfg, rho, ux, uy, h->lat[0], h->stream);
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  h->cur = 0;
+  h->steps = 0;
+  return LBM_OK;
+}
+
 const char *lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+struct lbm_batch {
+  std::vector<lbm_handle *> members;
+  int storage = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  lbm::BatchDomain *d_doms = nullptr;
+  lbm::BatchDomain *h_doms[2] = {nullptr, nullptr};  // pinned staging, alternating
+  hipEvent_t copied[2] = {nullptr, nullptr};         // staging buffer free again
+  int slot = 0;
+  int2 *d_tiles = nullptr;
+  int *d_ntiles = nullptr;
+  int ntiles = 0;
+  size_t dom_cap = 0, tile_cap = 0;
+  int cus = 1;
+  int blocks_per_cu = 8;
+  std::map<int, hipGraphExec_t> graphs;  // keyed by (tick, grid)
+};
+
+namespace {
+
+void fill_domain(const lbm_handle *h, int stop_at, lbm::BatchDomain &d) {
+  const lbm::StepConfig &c = h->cfg;
+  d.lat[0] = h->lat[0];
+  d.lat[1] = h->lat[1];
+  d.chi_field = c.chi_field;
+  d.chi_x = c.chi_x;
+  d.chi_y = c.chi_y;
+  d.pitch = c.pitch;
+  d.ps = c.plane_stride;
+  d.nx = c.nx;
+  d.ny = c.ny;
+  d.variant = c.variant;
+  d.chi_mode = c.chi_mode;
+  d.parity = h->cur;
+  d.stop_at = stop_at;
+  for (int k = 0; k < 9; ++k) d.s[k] = c.s[k];
+  d.n = c.n;
+  d.m = c.m;
+  d.rho_b = c.rho_b;
+  d.ubx = c.ubx;
+  d.uby = c.uby;
+  for (int k = 0; k < 3; ++k) d.dcf[k] = c.dcf[k];
+  for (int i = 0; i < 9; ++i) {
+    d.scale[i] = lbm::storage_scale(c, i);
+    d.inv_scale[i] = 1.0 / d.scale[i];
+  }
+}
+
+void free_graphs(lbm_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+// Instantiated graph of `tick` batched launches (k = 0 .. tick-1).
+int batch_graph(lbm_batch *b, int tick, hipGraphExec_t *out) {
+  const int grid = b->cus * b->blocks_per_cu;
+  const int key = tick * 4096 + b->blocks_per_cu;
+  auto it = b->graphs.find(key);
+  if (it != b->graphs.end()) {
+    *out = it->second;
+    return LBM_OK;
+  }
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < tick && e == hipSuccess; ++k)
+    e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, b->stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  b->graphs[key] = ex;
+  *out = ex;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  free_graphs(b);
+  if (b->d_doms) (void)hipFree(b->d_doms);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_ntiles) (void)hipFree(b->d_ntiles);
+  for (int k = 0; k < 2; ++k) {
+    if (b->h_doms[k]) (void)hipHostFree(b->h_doms[k]);
+    if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+  }
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+}  // extern "C"
+
+namespace {
+
+int validate_members(lbm_handle *const *members, int32_t count) {
+  if (!members || count < 1) return fail(LBM_EINVAL, "a batch needs at least one member");
+  for (int32_t i = 0; i < count; ++i) {
+    if (!members[i]) return fail(LBM_EINVAL, "NULL member");
+    if (members[i]->user.storage != members[0]->user.storage)
+      return fail(LBM_EINVAL, "all members must share the storage mode");
+    if (members[i]->device != members[0]->device)
+      return fail(LBM_EINVAL, "all members must live on one device");
+    for (int32_t j = 0; j < i; ++j)
+      if (members[j] == members[i]) return fail(LBM_EINVAL, "members must be distinct");
+  }
+  return LBM_OK;
+}
+
+// Rebuild the tile table for a new member list; reuses the device buffers
+// (and so the captured graphs) whenever they are large enough.
+int batch_set_members_impl(lbm_batch *b, lbm_handle *const *members, int32_t count) {
+  int rc = validate_members(members, count);
+  if (rc) return rc;
+  if (!b->members.empty() && members[0]->user.storage != b->storage)
+    return fail(LBM_EINVAL, "members must keep the batch's storage mode");
+  std::vector<int2> tiles;
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t cells = members[i]->user.nx * members[i]->user.ny;
+    for (int64_t c0 = 0; c0 < cells; c0 += lbm::BATCH_TILE) tiles.push_back(make_int2(i, (int)c0));
+  }
+  if (tiles.size() > (size_t)0x7fffffff) return fail(LBM_EINVAL, "too many tiles");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  for (int32_t i = 0; i < count; ++i) HIP_TRY(hipStreamSynchronize(members[i]->stream), "hipStreamSynchronize");
+  if ((size_t)count > b->dom_cap || tiles.size() > b->tile_cap) {
+    // grow: the old buffers (and every graph that points at them) go away
+    free_graphs(b);
+    if (b->d_doms) (void)hipFree(b->d_doms);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    for (int k = 0; k < 2; ++k)
+      if (b->h_doms[k]) (void)hipHostFree(b->h_doms[k]);
+    b->d_doms = nullptr;
+    b->d_tiles = nullptr;
+    b->h_doms[0] = b->h_doms[1] = nullptr;
+    b->dom_cap = b->tile_cap = 0;
+    const size_t dc = std::max<size_t>((size_t)count, 2 * b->members.size());
+    const size_t tc = std::max<size_t>(tiles.size(), (size_t)(1.5 * tiles.size()));
+    hipError_t e = hipMalloc((void **)&b->d_doms, sizeof(lbm::BatchDomain) * dc);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sizeof(int2) * tc);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+      e = hipHostMalloc((void **)&b->h_doms[k], sizeof(lbm::BatchDomain) * dc, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "batch buffers");
+    b->dom_cap = dc;
+    b->tile_cap = tc;
+  }
+  b->ntiles = (int)tiles.size();
+  HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice),
+          "hipMemcpy(tiles)");
+  HIP_TRY(hipMemcpy(b->d_ntiles, &b->ntiles, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy(ntiles)");
+  b->members.assign(members, members + count);
+  b->storage = members[0]->user.storage;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(lbm_handle *const *members, int32_t count, void *stream,
+                     lbm_batch **out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_members(members, count);
+  if (rc) return rc;
+  lbm_batch *b = new (std::nothrow) lbm_batch();
+  if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+  hipError_t e = hipSuccess;
+  if (stream) {
+    b->stream = (hipStream_t)stream;
+  } else {
+    e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    b->own_stream = e == hipSuccess;
+  }
+  int dev = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_ntiles, sizeof(int));
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    lbm_batch_destroy(b);
+    return hip_fail(e, "lbm_batch_create");
+  }
+  rc = batch_set_members_impl(b, members, count);
+  if (rc) {
+    lbm_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_set_members(lbm_batch *b, lbm_handle *const *members, int32_t count) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  return batch_set_members_impl(b, members, count);
+}
+
+int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "blocks_per_cu must be 1..64");
+  b->blocks_per_cu = blocks_per_cu;
+  return LBM_OK;
+}
+
+int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (tick < 1 || tick > 4096) return fail(LBM_EINVAL, "tick must be 1..4096");
+  const size_t n = b->members.size();
+  if (member_steps)
+    for (size_t i = 0; i < n; ++i)
+      if (member_steps[i] < 0 || member_steps[i] > tick)
+        return fail(LBM_EINVAL, "member steps must lie in [0, tick]");
+  // descriptors go through one of two pinned staging buffers; the copy that
+  // last read this buffer (two ticks ago) must have finished
+  const int sl = b->slot;
+  b->slot ^= 1;
+  HIP_TRY(hipEventSynchronize(b->copied[sl]), "hipEventSynchronize");
+  lbm::BatchDomain *hd = b->h_doms[sl];
+  for (size_t i = 0; i < n; ++i)
+    fill_domain(b->members[i], member_steps ? member_steps[i] : tick, hd[i]);
+  // stream order puts this copy after the previous tick's launches, which are
+  // the last readers of d_doms
+  HIP_TRY(hipMemcpyAsync(b->d_doms, hd, sizeof(lbm::BatchDomain) * n,
+                         hipMemcpyHostToDevice, b->stream), "hipMemcpy(descriptors)");
+  HIP_TRY(hipEventRecord(b->copied[sl], b->stream), "hipEventRecord");
+  hipGraphExec_t ex = nullptr;
+  int rc = batch_graph(b, tick, &ex);
+  if (rc) return rc;
+  HIP_TRY(hipGraphLaunch(ex, b->stream), "hipGraphLaunch");
+  for (size_t i = 0; i < n; ++i) {
+    const int st = member_steps ? member_steps[i] : tick;
+    b->members[i]->cur ^= st & 1;
+    b->members[i]->steps += st;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t n) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  const int64_t chunk = 4096;
+  while (n > 0) {
+    const int32_t t = (int32_t)(n < chunk ? n : chunk);
+    int rc = lbm_batch_tick(b, t, nullptr);
+    if (rc) return rc;
+    n -= t;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_sync(lbm_batch *b) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
 
 int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
   if (!dst || !src || (bytes & 15)) return fail(LBM_EINVAL, "copy needs non-NULL pointers and bytes % 16 == 0");
@@ -621,13 +910,12 @@ int vn_amplification_dev(const lbm_vn_params *params, int64_t nparams, int64_t n
   }
   hipStream_t s = (hipStream_t)stream;
   lbm::VnParamsDev *dp = nullptr;
-  HIP_TRY(hipMalloc((void **)&dp, sizeof(lbm::VnParamsDev) * nparams), "hipMalloc(vn params)");
+  HIP_TRY(hipMallocAsync((void **)&dp, sizeof(lbm::VnParamsDev) * nparams, s), "hipMallocAsync(vn params)");
+  // a pageable source makes this copy complete before the call returns
   hipError_t e = hipMemcpyAsync(dp, hp.data(), sizeof(lbm::VnParamsDev) * nparams,
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = lbm::launch_vn(dp, (int)nparams, nk, kx, ky, eig, G, s);
-  // the parameter block must live until the kernel has read it
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(dp);
+  (void)hipFreeAsync(dp, s);
   if (e != hipSuccess) return hip_fail(e, "Von Neumann kernel");
   return LBM_OK;
 }

@@ -58,6 +58,25 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes,
                        hipStream_t stream);
 int elem_bytes_of(int storage);
 
+// Batched stepping (lbm_batch.hip). One descriptor per member domain.
+constexpr int BATCH_TILE = 256;  // cells per tile = threads per workgroup
+struct BatchDomain {
+  void *lat[2];          // lat[parity] is current at the start of a tick
+  const void *chi_field; // compute type, CHI_FIELD
+  const void *chi_x, *chi_y;
+  int64_t pitch, ps;
+  int nx, ny, variant, chi_mode;
+  int parity;            // current lattice at the start of the tick
+  int stop_at;           // steps this domain takes in the tick
+  double s[9];
+  double n, m, rho_b, ubx, uby;
+  double dcf[3];
+  double scale[9], inv_scale[9];
+};
+hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
+                        const int *ntiles_dev, int grid, int k,
+                        hipStream_t stream);
+
 // Von Neumann (lbm_vn.hip).
 struct VnParamsDev {
   double s[9];

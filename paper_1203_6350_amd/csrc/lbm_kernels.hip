@@ -397,13 +397,12 @@ __global__ void init_kernel(DevLat L, const double *__restrict__ rho,
   for (int i = 0; i < 9; ++i) {
     const int xs = wrapi(x + cx_of(i), L.nx), ys = wrapi(y + cy_of(i), L.ny);
     const int64_t src = (int64_t)ys * L.nx + xs;
-    double dr = 0.0, djx = 0.0, djy = 0.0;
-    if (rho) {
-      dr = rho[src] - L.rho_b;
-      // j - j_b = drho u + rho_b (u - u_b)
-      djx = dr * ux[src] + L.rho_b * (ux[src] - L.ubx);
-      djy = dr * uy[src] + L.rho_b * (uy[src] - L.uby);
-    }
+    // missing fields take the base value
+    const double dr = rho ? rho[src] - L.rho_b : 0.0;
+    const double u = ux ? ux[src] : L.ubx, w = uy ? uy[src] : L.uby;
+    // j - j_b = drho u + rho_b (u - u_b)
+    const double djx = dr * u + L.rho_b * (u - L.ubx);
+    const double djy = dr * w + L.rho_b * (w - L.uby);
     const double v = feq_dev_i(i, dr, djx, djy, L.rho_b, L.ubx, L.uby);
     store_dev<S>(dst + i * L.ps + (int64_t)y * L.pitch + x, v, L.inv_scale[i]);
   }

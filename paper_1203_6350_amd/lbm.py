@@ -109,6 +109,13 @@ def load(path: str | None = None):
         "vn_amplification": [ctypes.POINTER(lbm_vn_params), i64, _DP, _DP, _DP, _DP],
         "vn_amplification_dev": [ctypes.POINTER(lbm_vn_params), i64, i64, vp, vp, vp, vp, vp],
         "lbm_device_copy": [vp, vp, sz, vp],
+        "lbm_batch_create": [ctypes.POINTER(_H), i32, vp, ctypes.POINTER(_H)],
+        "lbm_batch_step": [_H, i64],
+        "lbm_batch_tick": [_H, i32, ctypes.POINTER(ctypes.c_int32)],
+        "lbm_batch_set_grid": [_H, i32],
+        "lbm_batch_set_members": [_H, ctypes.POINTER(_H), i32],
+        "lbm_init_fields_dev": [_H, vp, vp, vp],
+        "lbm_batch_sync": [_H],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -116,6 +123,8 @@ def load(path: str | None = None):
         f.restype = ctypes.c_int
     L.lbm_destroy.argtypes = [_H]
     L.lbm_destroy.restype = None
+    L.lbm_batch_destroy.argtypes = [_H]
+    L.lbm_batch_destroy.restype = None
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -430,3 +439,80 @@ class Lattice:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------- batches
+
+def lbm_batch_create(handles, stream=None):
+    arr = (_H * len(handles))(*[h.value if isinstance(h, _H) else h for h in handles])
+    b = _H()
+    _check(load().lbm_batch_create(arr, len(handles), _stream_ptr(stream), ctypes.byref(b)))
+    return b
+
+
+def lbm_batch_set_members(b, handles):
+    arr = (_H * len(handles))(*[h.value if isinstance(h, _H) else h for h in handles])
+    _check(load().lbm_batch_set_members(b, arr, len(handles)))
+
+
+def lbm_init_fields_dev(h, rho=None, ux=None, uy=None):
+    _check(load().lbm_init_fields_dev(h, _dev(rho), _dev(ux), _dev(uy)))
+
+
+def lbm_batch_step(b, n):
+    _check(load().lbm_batch_step(b, int(n)))
+
+
+def lbm_batch_tick(b, tick, member_steps=None):
+    ms = None
+    if member_steps is not None:
+        arr = (ctypes.c_int32 * len(member_steps))(*[int(x) for x in member_steps])
+        ms = arr
+    _check(load().lbm_batch_tick(b, int(tick), ms))
+
+
+def lbm_batch_set_grid(b, blocks_per_cu):
+    _check(load().lbm_batch_set_grid(b, int(blocks_per_cu)))
+
+
+def lbm_batch_sync(b):
+    _check(load().lbm_batch_sync(b))
+
+
+def lbm_batch_destroy(b):
+    if b is not None:
+        load().lbm_batch_destroy(b)
+
+
+class Batch:
+    """Many lattices stepped by one persistent launch per step (HIP graphs).
+
+    The batch keeps references to its member Lattice objects; members must not
+    be stepped on their own while the batch has work in flight (``sync()``)."""
+
+    def __init__(self, lattices, stream=None):
+        self.members = list(lattices)
+        self.b = lbm_batch_create([m.h for m in self.members], stream)
+
+    def step(self, n):
+        lbm_batch_step(self.b, n)
+
+    def tick(self, tick, member_steps=None):
+        lbm_batch_tick(self.b, tick, member_steps)
+
+    def set_grid(self, blocks_per_cu):
+        lbm_batch_set_grid(self.b, blocks_per_cu)
+
+    def sync(self):
+        lbm_batch_sync(self.b)
+
+    def close(self):
+        if self.b is not None:
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

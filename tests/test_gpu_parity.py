@@ -384,3 +384,94 @@ def test_autotune_keeps_state():
     assert best in TUNINGS and ms > 0
     assert lat.tuning() == best
     lat.close()
+
+
+# ------------------------------------------------------------------ batches
+
+def batch_members(count, seed, storage="f32", max_n=96):
+    g = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        nx = int(g.integers(1, max_n))
+        ny = int(g.integers(1, max_n))
+        rho, ux, uy, chi = random_case(nx, ny, seed * 1000 + k, u0=float(g.uniform(0, 0.05)))
+        var = ("none", "I", "II", "III")[k % 4]
+        if var == "I":
+            chi = np.minimum(chi, 0.1)
+        q = (1.0, float(ux.mean()), 0.0)
+        kind = k % 3
+        out.append(dict(nx=nx, ny=ny, rho=rho, ux=ux, uy=uy, chi=chi, q=q, variant=var,
+                        kind=kind, ub=float(ux.mean()),
+                        s=(0, 0, 0) + tuple(g.uniform(1.0, 1.95, 6))))
+    return out
+
+
+def make_member(m, storage):
+    lat = lbm.Lattice(m["nx"], m["ny"], rho=m["rho"], ux=m["ux"], uy=m["uy"], storage=storage,
+                      variant=m["variant"], s=m["s"], ux_base=m["ub"], f16_scale=1e-3)
+    if m["kind"] == 0:
+        lat.set_sponge(m["chi"], m["q"])
+    elif m["kind"] == 1:
+        lat.set_sponge_separable(m["chi"].max(axis=0), m["chi"].max(axis=1), "max", m["q"])
+    else:
+        lat.set_sponge(None, m["q"])
+    return lat
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_batch_equals_alone_bitwise(storage):
+    """A member stepped in the batch (graph replays of the persistent launch,
+    with eager work between replays) is bit-identical to it stepped alone."""
+    say("case: batch vs alone", storage)
+    members = batch_members(13, 5, storage)
+    alone = []
+    for m in members:
+        lat = make_member(m, storage)
+        lat.step(70)
+        alone.append(lat.save_state())
+        lat.close()
+    lats = [make_member(m, storage) for m in members]
+    b = lbm.Batch(lats)
+    b.step(64)     # one graph of 64 launches
+    b.sync()
+    lats[0].diagnostics()  # eager work between replays
+    b.step(6)      # a second graph
+    b.sync()
+    for lat, ref in zip(lats, alone):
+        np.testing.assert_array_equal(lat.save_state(), ref)
+    # the batch replays the cached graphs again
+    b.step(70)
+    b.sync()
+    for m, lat in zip(members, lats):
+        ref = make_member(m, storage)
+        ref.step(140)
+        np.testing.assert_array_equal(lat.save_state(), ref.save_state())
+        ref.close()
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_tick_partial_steps_and_oracle():
+    """Members taking fewer steps than the tick keep their state; results match
+    the oracle."""
+    members = batch_members(6, 9, "f64", max_n=40)
+    lats = [make_member(m, "f64") for m in members]
+    b = lbm.Batch(lats)
+    steps = [5, 0, 12, 1, 12, 7]
+    b.tick(12, steps)
+    b.tick(12, steps)
+    b.sync()
+    for m, lat, st in zip(members, lats, steps):
+        chi = None
+        if m["kind"] == 0:
+            chi = m["chi"]
+        elif m["kind"] == 1:
+            chi = wl.sponge_2d(m["chi"].max(axis=0), m["chi"].max(axis=1))
+        ref = oracle.step(oracle.feq_field(m["rho"], m["ux"], m["uy"]), 2 * st, s=m["s"], chi=chi,
+                          qref=m["q"], variant=m["variant"])
+        assert rel_max(lat.populations(), ref) <= 1e-12
+        assert lat.info().steps_done == 2 * st
+    b.close()
+    for lat in lats:
+        lat.close()
