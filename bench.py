@@ -201,6 +201,63 @@ def serving_leg(torch, rates=(50, 100, 200, 500), count=2000, warmup=200, budget
     return out
 
 
+def characteristics(rho, ux, rho0, u0, lo, hi):
+    """Right- and left-going acoustic parts p'_+- = (p' +- rho0 c_s u'_x)/2 of a
+    y-uniform state on the physical x-range [lo, hi)."""
+    cs = 1.0 / math.sqrt(3.0)
+    p = (rho[lo:hi] - rho0) / 3.0
+    u = ux[lo:hi] - u0
+    return 0.5 * (p + rho0 * cs * u), 0.5 * (p - rho0 * cs * u)
+
+
+def precision_leg(lbm, wl, n=2048, steps=4000, chis=(0.05, 0.2, 0.5), width=48):
+    """Plane packet (amplitude 1e-4, wavelength 64, 8 wavelengths) in Mach-0.1
+    flow entering a 48-cell x-sponge, Type II. Each storage mode and base
+    against the FP64 oracle on an n x 1 lattice (exact: a y-uniform state with
+    an x-only sponge evolves row by row like the one-row lattice)."""
+    import numpy as np
+    import oracle
+    u0 = 0.1 * wl.CS
+    rho, ux, uy = wl.plane_packet(n, n, amp=1e-4, wavelength=64.0, n_wavelengths=8,
+                                  centre=n / 2, u0=u0)
+    cx = wl.quadratic_ramp_1d(n, width, 1.0)
+    lo, hi = width, n - width
+    p0p, _ = characteristics(rho[0], ux[0], 1.0, u0, lo, hi)
+    norm0 = float(np.sqrt((p0p ** 2).sum()))
+    out = {}
+    for chi_max in chis:
+        q = (1.0, u0, 0.0)
+        f1 = oracle.feq_field(rho[:1], ux[:1], uy[:1])
+        ref = oracle.step(f1, steps, chi=chi_max * cx[None, :], qref=q, variant="II")
+        rr, ur, _ = oracle.moments(ref)
+        rp, rm = characteristics(rr[0], ur[0], 1.0, u0, lo, hi)
+        row = {"oracle_R": float(np.sqrt((rm ** 2).sum())) / norm0,
+               "oracle_T": float(np.sqrt((rp ** 2).sum())) / norm0}
+        for storage in ("f64", "f32", "f16"):
+            for base in ("rest", "ref"):
+                lat = lbm.Lattice(n, n, rho=rho, ux=ux, uy=uy, storage=storage, variant="II",
+                                  ux_base=u0 if base == "ref" else 0.0, f16_scale=1e-4)
+                lat.set_sponge_separable(chi_max * cx, None, "max", q)
+                lat.step(steps)
+                g_rho, g_ux, _ = lat.moments()
+                lat.close()
+                pr = g_rho - 1.0
+                pref = rr[0] - 1.0
+                p_init = rho[0] - 1.0
+                sq = ((pr - pref[None, :]) ** 2).sum() / n
+                err = float(np.sqrt(sq / (pref ** 2).sum()))
+                err0 = float(np.sqrt(sq / (p_init ** 2).sum()))
+                rows_equal = bool((g_rho == g_rho[:1]).all())
+                gp, gm = characteristics(g_rho[0], g_ux[0], 1.0, u0, lo, hi)
+                row["%s_%s" % (storage, base)] = {
+                    "pprime_rel_l2": err, "pprime_err_over_initial": err0,
+                    "rows_identical": rows_equal,
+                    "R": float(np.sqrt((gm ** 2).sum())) / norm0,
+                    "T": float(np.sqrt((gp ** 2).sum())) / norm0}
+        out["chi_max=%g" % chi_max] = row
+    return out
+
+
 def cpu_baseline(spec, fields, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -232,6 +289,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -301,6 +359,9 @@ def main():
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)
+    if not args.no_precision:
+        print("bench: precision study 2048^2, 4000 steps", file=sys.stderr, flush=True)
+        out["precision"] = precision_leg(lbm, wl)
     if not args.no_serve:
         out["served"] = serving_leg(torch, count=args.serve_requests,
                                     warmup=args.serve_requests // 10)

@@ -475,3 +475,95 @@ def test_batch_tick_partial_steps_and_oracle():
     b.close()
     for lat in lats:
         lat.close()
+
+
+# ------------------------------------------------------------------ full-size property checks
+
+@pytest.mark.parametrize("storage,base,bar", [("f64", "rest", 1e-12), ("f64", "ref", 1e-12),
+                                              ("f32", "ref", 1e-5), ("f16", "ref", 1e-3)])
+def test_plane_packet_2048_against_one_row_oracle(storage, base, bar):
+    """2048^2 plane packet in Mach-0.1 flow through a 48-cell x-sponge (Type II,
+    chi_max = 0.2, 4000 steps): every GPU row is bit-identical and equals the
+    one-row FP64 oracle (y-invariance reduction). FP64: populations within
+    1e-12 of max |f|. FP32/FP16: p' error relative to the initial wave norm
+    (the sponge absorbs the wave, while rounding noise does not shrink with
+    it; the error relative to the absorbed remainder is printed as well)."""
+    n, steps = 2048, 4000
+    say("case: plane packet 2048^2", storage, base)
+    u0 = 0.1 * wl.CS
+    rho, ux, uy = wl.plane_packet(n, n, amp=1e-4, centre=n / 2, u0=u0)
+    cx = wl.quadratic_ramp_1d(n, 48, 0.2)
+    q = (1.0, u0, 0.0)
+    f0 = oracle.feq_field(rho[:1], ux[:1], uy[:1])
+    ref = oracle.step(f0, steps, chi=cx[None, :], qref=q, variant="II")
+    rr = ref.sum(axis=0)[0] - 1.0
+    r0 = f0.sum(axis=0)[0] - 1.0
+    lat = lbm.Lattice(n, n, rho=rho, ux=ux, uy=uy, storage=storage, variant="II",
+                      ux_base=u0 if base == "ref" else 0.0, f16_scale=1e-4)
+    lat.set_sponge_separable(cx, None, "max", q)
+    lat.step(steps)
+    if storage == "f64":
+        f = lat.populations()
+        lat.close()
+        assert (f == f[:, :1, :]).all()  # rows bit-identical
+        err = np.abs(f[:, 0, :] - ref[:, 0, :]).max() / np.abs(ref).max()
+        say("  populations max rel err %.3e" % err)
+        assert err <= bar
+        return
+    g, _, _ = lat.moments()
+    lat.close()
+    assert (g == g[:1]).all()  # rows bit-identical
+    gr = g[0] - 1.0
+    e0 = math.sqrt(((gr - rr) ** 2).sum() / (r0 ** 2).sum())
+    eT = math.sqrt(((gr - rr) ** 2).sum() / (rr ** 2).sum())
+    say("  p' error / |p'(0)| %.3e ; / |p'(T)| %.3e" % (e0, eT))
+    assert e0 <= bar
+
+
+def test_full_size_4096_sampled_light_cone():
+    """The benchmark workload at full size (4096^2, FP32, Mach 0.2, 32 pulses,
+    64-cell sponge, Type II) in the benchmark's launch configuration: after T
+    steps, sampled cells (corners with the periodic wrap, sponge, interior
+    pulses) match the oracle run on the (4T+1)^2 neighbourhood that holds
+    their light cone."""
+    spec = wl.large_c2(variant="II", storage="f32")
+    T = 40
+    say("case: 4096^2 sampled light-cone parity, T =", T)
+    rho, ux, uy = spec.fields()
+    cx, cy = spec.chi_1d()
+    lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage="f32", variant="II",
+                      ux_base=spec.u0)
+    lat.set_sponge_separable(cx, cy, "max", spec.qref)
+    lat.autotune(reps=3)
+    lat.step(T)
+    r_gpu, _, _ = lat.moments()
+    lat.close()
+    chi2 = wl.sponge_2d(cx, cy)
+    n = spec.nx
+    H = 2 * T
+    g = np.random.default_rng(0)
+    centres = [(0, 0), (n - 1, 5), (30, n - 2), (n // 2, 10)]
+    centres += [(int(p[0]), int(p[1])) for p in spec.pulses[:4]]
+    centres += [tuple(int(v) for v in g.integers(0, n, 2)) for _ in range(4)]
+    num = den = 0.0
+    worst_abs = 0.0
+    for (x0, y0) in centres:
+        xs = (np.arange(x0 - H, x0 + H + 1)) % n
+        ys = (np.arange(y0 - H, y0 + H + 1)) % n
+        sub = np.ix_(ys, xs)
+        f0 = oracle.feq_field(rho[sub], ux[sub], uy[sub])
+        ref = oracle.step(f0, T, chi=chi2[sub], qref=spec.qref, variant="II")
+        rr = ref.sum(axis=0)
+        # cells whose light cone stays inside the patch
+        inner = np.ix_(ys[H - T:H + T + 1], xs[H - T:H + T + 1])
+        gp = r_gpu[inner] - 1.0
+        rp = rr[H - T:H + T + 1, H - T:H + T + 1] - 1.0
+        num += ((gp - rp) ** 2).sum()
+        den += (rp ** 2).sum()
+        worst_abs = max(worst_abs, np.abs(gp - rp).max())
+    # pooled over the samples (the pulse-centred patches carry the signal;
+    # far-field patches are zero to rounding on both sides)
+    e = math.sqrt(num / den)
+    say("  sampled p' rel L2 %.3e, max abs %.3e" % (e, worst_abs))
+    assert e <= 1e-5
+    assert worst_abs <= 1e-5 * 1e-4
