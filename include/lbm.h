@@ -191,10 +191,15 @@ int lbm_get_info(lbm_handle *h, lbm_info *info);
 typedef struct lbm_tuning {
   int32_t kernel;      /* 0: one cell per thread; 1: 16-byte vector rows
                           (4 cells FP32, 2 FP64, 8 FP16; needs nx % cells == 0,
-                          otherwise the library falls back to 0)            */
-  int32_t block;       /* threads per block: 64, 128, 256 or 512            */
+                          otherwise the library falls back to 0);
+                          2: two time steps per launch (each 64-lane wave
+                          owns a 60-column strip of a chunk of rows and
+                          reads/writes the lattice once per two steps; an
+                          odd remaining step uses kernel 0)                  */
+  int32_t block;       /* threads per block: 64, 128, 256 or 512 (kernel 2:
+                          64, 128 or 256)                                   */
   int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
-  int32_t pad_;
+  int32_t rows;        /* kernel 2: rows per chunk (16..1024), else ignored  */
 } lbm_tuning;
 
 int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t);
@@ -202,7 +207,7 @@ int lbm_get_tuning(lbm_handle *h, lbm_tuning *t);
 
 /* Time every candidate launch shape on the handle's own lattice (reps
  * launches each, after two warm-up launches; the state is not advanced),
- * keep the fastest and return it with its mean launch time in ms.
+ * keep the fastest and return it with its mean time per time step in ms.
  * best and best_ms may be NULL. Synchronises. */
 int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms);
 

@@ -75,12 +75,25 @@ __device__ __forceinline__ double fmaC<double>(double a, double b, double c) {
   return __builtin_fma(a, b, c);
 }
 
+// Reciprocal: the hardware FP32 reciprocal (within 1 ulp) in FP32; exact
+// division in FP64.
+template <typename C>
+__device__ __forceinline__ C recip(C x);
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+  return 1.0 / x;
+}
+
 // Deviation of the moment equilibria, dm^eq = m^eq(c_b + dc) - m^eq(c_b).
 template <typename C>
 __device__ __forceinline__ void meq_delta(C dr, C djx, C djy, C rho_b, C ubx,
                                           C uby, C out[9]) {
   const C rho = rho_b + dr;
-  const C inv = C(1) / rho;
+  const C inv = recip(rho);
   const C vx = djx - ubx * dr;
   const C vy = djy - uby * dr;
   // d(jx^2/rho), d(jy^2/rho), d(jx jy/rho)
@@ -126,9 +139,11 @@ __device__ __forceinline__ void collide(C g[9], C chi,
   C dr = dm[0], djx = dm[1], djy = dm[2];
   if (VAR != V_NONE) {
     const C nchi = p.n * chi, mchi = p.m * chi;
-    dr = fmaC(nchi, p.dcf0, dm[0]) / (C(1) + nchi);
-    djx = fmaC(mchi, p.dcf1, dm[1]) / (C(1) + mchi);
-    djy = fmaC(mchi, p.dcf2, dm[2]) / (C(1) + mchi);
+    const C inv_n = recip(C(1) + nchi);
+    const C inv_m = p.n == p.m ? inv_n : recip(C(1) + mchi);
+    dr = fmaC(nchi, p.dcf0, dm[0]) * inv_n;
+    djx = fmaC(mchi, p.dcf1, dm[1]) * inv_m;
+    djy = fmaC(mchi, p.dcf2, dm[2]) * inv_m;
   }
 
   // ---- equilibrium moments at the shifted state

@@ -203,6 +203,179 @@ __global__ __launch_bounds__(BX) void step_vec(
   for (int i = 0; i < 9; ++i) store16<NT>(dst + i * ps + r0 + x0, out[i]);
 }
 
+// ---------------------------------------------------------------- two steps per launch
+// Each wave owns a strip of STRIP = 60 output columns of one chunk of rows:
+// lane l holds column X0 - 2 + l (mod nx), so the 64 lanes cover the strip
+// plus two halo columns on each side. The wave marches down the rows. When
+// row a of the input lattice A arrives, the lanes compute the first step at
+// row a - 1 and the second step at row a - 2. Pulls along x come from the
+// neighbouring lanes (shuffles); pulls along y come from carried registers:
+// each row's nine populations are used by three consecutive rows, three by
+// each (c_y = -1 now, c_y = 0 one row later, c_y = +1 two rows later), so nine
+// carried values per step suffice. A lane's first-step result is valid on
+// lanes 1..62 and its second-step result on lanes 2..61, the strip's outputs.
+// The first-step result is rounded through the storage format before the
+// second step reads it, exactly as a stored and reloaded value would be, so
+// the result is bit-identical to two launches of the one-step kernels.
+constexpr int STRIP = 60;
+
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C roundtrip(typename Store<S>::C v,
+                                                          typename Store<S>::C scale,
+                                                          typename Store<S>::C inv_scale) {
+  S t;
+  Store<S>::store(&t, v, inv_scale);
+  return Store<S>::load(&t, scale);
+}
+
+template <typename C>
+__device__ __forceinline__ C lane_up(C v) {  // value of lane - 1
+  return __shfl_up(v, 1, 64);
+}
+template <typename C>
+__device__ __forceinline__ C lane_down(C v) {  // value of lane + 1
+  return __shfl_down(v, 1, 64);
+}
+
+// One first-or-second step at one row: rm = populations of the row above
+// (y - 1, gives c_y = +1 pulls: 2, 5, 6), r0 = this row (0, 1, 3), rp = the
+// row below (y + 1, gives 4, 7, 8). The x shifts come from the neighbours.
+template <typename C, int VAR>
+__device__ __forceinline__ void pull_collide(const C rm[9], const C r0[9], const C rp[9],
+                                             C chi, const CollideParams<C> &p, C out[9]) {
+  out[0] = r0[0];
+  out[1] = lane_up(r0[1]);
+  out[2] = rm[2];
+  out[3] = lane_down(r0[3]);
+  out[4] = rp[4];
+  out[5] = lane_up(rm[5]);
+  out[6] = lane_down(rm[6]);
+  out[7] = lane_down(rp[7]);
+  out[8] = lane_up(rp[8]);
+  collide<C, VAR>(out, chi, p);
+}
+
+template <typename S, int VAR, int CHI, int NW>
+__global__ __launch_bounds__(64 * NW) void step2_strip(
+    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
+    CollideParams<typename Store<S>::C> p,
+    const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix,
+    const typename Store<S>::C *__restrict__ chiy, int rows_per_chunk,
+    int nstrips, int nchunks, int wg_per_xcd, int nwg) {
+  typedef typename Store<S>::C C;
+  // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
+  // contiguous range of work so neighbouring strips share an L2
+  const int v = (blockIdx.x & 7) * wg_per_xcd + (blockIdx.x >> 3);
+  if (v >= nwg) return;
+  const int lane = threadIdx.x & 63;
+  const int item = v * NW + (threadIdx.x >> 6);
+  if (item >= nstrips * nchunks) return;
+  const int chunk = item / nstrips, strip = item - chunk * nstrips;
+  const int X0 = strip * STRIP;
+  const int Y0 = chunk * rows_per_chunk;
+  const int Y1 = min(Y0 + rows_per_chunk, L.ny);
+  const int nx = L.nx, ny = L.ny;
+  int col = (X0 - 2 + lane) % nx;
+  if (col < 0) col += nx;
+  const int64_t ps = L.ps;
+  const bool store_lane = lane >= 2 && lane <= STRIP + 1 && X0 + lane - 2 < nx;
+  C cx_chi = C(0);
+  if (CHI == CHI_SEP_MAX || CHI == CHI_SEP_SUM) cx_chi = chix[col];
+
+  // carried values: A rows a-1 (all) and a-2 (2, 5, 6); B1 rows b-1, b-2 likewise
+  C a_m1[9], a_m2[9], b_m1[9], b_m2[9];
+  // periodic row indices, advanced incrementally (one wrap test per row)
+  auto wrap_row = [&](int a) {
+    int r = a % ny;
+    return r < 0 ? r + ny : r;
+  };
+  auto next_row = [&](int r) { return r + 1 == ny ? 0 : r + 1; };
+  auto load_row = [&](int r, C out[9]) {
+    const int64_t off = (int64_t)r * L.pitch + col;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = Store<S>::load(src + i * ps + off, L.scale[i]);
+  };
+  auto chi_row = [&](int r) -> C {
+    if (CHI == CHI_ZERO) return C(0);
+    if (CHI == CHI_FIELD) return chi_field[(int64_t)r * L.pitch + col];
+    const C b = chiy[r];
+    if (CHI == CHI_SEP_MAX) return cx_chi > b ? cx_chi : b;
+    return cx_chi + b;
+  };
+  int r_ld = wrap_row(Y0 - 2);  // row of the load in flight (a + 1 after the top)
+  int r_m1 = wrap_row(Y0 - 3);  // row a - 1 during iteration a
+  int r_m2 = wrap_row(Y0 - 4);  // row a - 2 during iteration a
+  C nxt[9];
+  load_row(r_ld, nxt);
+  for (int a = Y0 - 2; a < Y1 + 2; ++a) {
+    C cur[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cur[i] = nxt[i];
+    r_ld = next_row(r_ld);
+    if (a + 1 < Y1 + 2) load_row(r_ld, nxt);  // one row ahead
+    if (a >= Y0) {
+      // first step at row a - 1 from A rows a - 2, a - 1, a
+      C b[9];
+      pull_collide<C, VAR>(a_m2, a_m1, cur, chi_row(r_m1), p, b);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) b[i] = roundtrip<S>(b[i], L.scale[i], L.inv_scale[i]);
+      if (a >= Y0 + 2) {
+        // second step at row a - 2 from B1 rows a - 3, a - 2, a - 1
+        // (the first of them, Y0 - 1, exists from a = Y0 + 2 on)
+        C o[9];
+        pull_collide<C, VAR>(b_m2, b_m1, b, chi_row(r_m2), p, o);
+        if (store_lane) {
+          const int64_t off = (int64_t)(a - 2) * L.pitch + (X0 + lane - 2);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) Store<S>::store(dst + i * ps + off, o[i], L.inv_scale[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        b_m2[i] = b_m1[i];
+        b_m1[i] = b[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      a_m2[i] = a_m1[i];
+      a_m1[i] = cur[i];
+    }
+    r_m2 = r_m1;
+    r_m1 = next_row(r_m1);
+  }
+}
+
+template <typename S, int VAR, int CHI, int NW>
+static hipError_t launch_two_t(const StepConfig &c, const void *src, void *dst,
+                               hipStream_t stream) {
+  typedef typename Store<S>::C C;
+  Lat<S> L = make_lat<S>(c);
+  CollideParams<C> p = make_params<C>(c);
+  const int rows = c.rows > 0 ? c.rows : 64;
+  const int nstrips = (c.nx + STRIP - 1) / STRIP;
+  const int nchunks = (c.ny + rows - 1) / rows;
+  const int64_t items = (int64_t)nstrips * nchunks;
+  const int64_t nwg = (items + NW - 1) / NW;
+  const int64_t per_xcd = (nwg + 7) / 8;
+  if (8 * per_xcd > 0x7fffffff) return hipErrorInvalidValue;
+  step2_strip<S, VAR, CHI, NW><<<dim3((unsigned)(8 * per_xcd)), dim3(64 * NW), 0, stream>>>(
+      (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
+      (const C *)c.chi_y, rows, nstrips, nchunks, (int)per_xcd, (int)nwg);
+  return hipGetLastError();
+}
+
+template <typename S, int VAR, int CHI>
+static hipError_t launch_two(const StepConfig &c, const void *src, void *dst,
+                             hipStream_t stream) {
+  switch (c.block) {
+    case 64: return launch_two_t<S, VAR, CHI, 1>(c, src, dst, stream);
+    case 128: return launch_two_t<S, VAR, CHI, 2>(c, src, dst, stream);
+    default: return launch_two_t<S, VAR, CHI, 4>(c, src, dst, stream);
+  }
+}
+
 template <typename S, int VAR, int CHI, int BX>
 static hipError_t launch_generic(const StepConfig &c, const void *src, void *dst,
                                  hipStream_t stream) {
@@ -237,6 +410,12 @@ bool vec_supported(const StepConfig &c) {
 }
 
 template <typename S, int VAR, int CHI>
+static hipError_t launch_step2_t(const StepConfig &c, const void *src,
+                                 void *dst, hipStream_t stream) {
+  return launch_two<S, VAR, CHI>(c, src, dst, stream);
+}
+
+template <typename S, int VAR, int CHI>
 static hipError_t launch_step_t(const StepConfig &c, const void *src,
                                 void *dst, hipStream_t stream) {
   const int kernel = c.kernel == KERNEL_VEC && vec_supported(c) ? KERNEL_VEC : KERNEL_GENERIC;
@@ -266,7 +445,16 @@ static hipError_t launch_step_t(const StepConfig &c, const void *src,
 
 template <typename S, int VAR>
 static hipError_t dispatch_chi(const StepConfig &c, const void *src, void *dst,
-                               hipStream_t s) {
+                               hipStream_t s, bool two) {
+  if (two) {
+    switch (c.chi_mode) {
+      case CHI_ZERO: return launch_step2_t<S, VAR, CHI_ZERO>(c, src, dst, s);
+      case CHI_FIELD: return launch_step2_t<S, VAR, CHI_FIELD>(c, src, dst, s);
+      case CHI_SEP_MAX: return launch_step2_t<S, VAR, CHI_SEP_MAX>(c, src, dst, s);
+      case CHI_SEP_SUM: return launch_step2_t<S, VAR, CHI_SEP_SUM>(c, src, dst, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (c.chi_mode) {
     case CHI_ZERO: return launch_step_t<S, VAR, CHI_ZERO>(c, src, dst, s);
     case CHI_FIELD: return launch_step_t<S, VAR, CHI_FIELD>(c, src, dst, s);
@@ -278,12 +466,12 @@ static hipError_t dispatch_chi(const StepConfig &c, const void *src, void *dst,
 
 template <typename S>
 static hipError_t dispatch_var(const StepConfig &c, const void *src, void *dst,
-                               hipStream_t s) {
+                               hipStream_t s, bool two) {
   switch (c.variant) {
-    case V_NONE: return dispatch_chi<S, V_NONE>(c, src, dst, s);
-    case V_I: return dispatch_chi<S, V_I>(c, src, dst, s);
-    case V_II: return dispatch_chi<S, V_II>(c, src, dst, s);
-    case V_III: return dispatch_chi<S, V_III>(c, src, dst, s);
+    case V_NONE: return dispatch_chi<S, V_NONE>(c, src, dst, s, two);
+    case V_I: return dispatch_chi<S, V_I>(c, src, dst, s, two);
+    case V_II: return dispatch_chi<S, V_II>(c, src, dst, s, two);
+    case V_III: return dispatch_chi<S, V_III>(c, src, dst, s, two);
   }
   return hipErrorInvalidValue;
 }
@@ -291,9 +479,19 @@ static hipError_t dispatch_var(const StepConfig &c, const void *src, void *dst,
 hipError_t launch_step(const StepConfig &c, const void *src, void *dst,
                        hipStream_t stream) {
   switch (c.storage) {
-    case 0: return dispatch_var<double>(c, src, dst, stream);
-    case 1: return dispatch_var<float>(c, src, dst, stream);
-    case 2: return dispatch_var<__half>(c, src, dst, stream);
+    case 0: return dispatch_var<double>(c, src, dst, stream, false);
+    case 1: return dispatch_var<float>(c, src, dst, stream, false);
+    case 2: return dispatch_var<__half>(c, src, dst, stream, false);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_two_steps(const StepConfig &c, const void *src, void *dst,
+                            hipStream_t stream) {
+  switch (c.storage) {
+    case 0: return dispatch_var<double>(c, src, dst, stream, true);
+    case 1: return dispatch_var<float>(c, src, dst, stream, true);
+    case 2: return dispatch_var<__half>(c, src, dst, stream, true);
   }
   return hipErrorInvalidValue;
 }

@@ -51,10 +51,11 @@ class lbm_info(ctypes.Structure):
 
 class lbm_tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("nontemporal", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("nontemporal", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"kernel": self.kernel, "block": self.block, "nontemporal": self.nontemporal}
+        return {"kernel": self.kernel, "block": self.block, "nontemporal": self.nontemporal,
+                "rows": self.rows}
 
 
 class lbm_vn_params(ctypes.Structure):
@@ -281,8 +282,8 @@ def lbm_set_populations(h, f):
     _check(load().lbm_set_populations(h, pa))
 
 
-def lbm_set_tuning(h, kernel=1, block=256, nontemporal=0):
-    t = lbm_tuning(int(kernel), int(block), int(nontemporal), 0)
+def lbm_set_tuning(h, kernel=1, block=256, nontemporal=0, rows=0):
+    t = lbm_tuning(int(kernel), int(block), int(nontemporal), int(rows))
     _check(load().lbm_set_tuning(h, ctypes.byref(t)))
 
 

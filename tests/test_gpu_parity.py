@@ -336,16 +336,21 @@ def test_vn_paper_thresholds_on_gpu():
 
 # ------------------------------------------------------------------ launch shapes
 
-TUNINGS = [dict(kernel=k, block=b, nontemporal=nt) for k in (0, 1) for b in (64, 128, 256, 512)
-           for nt in ((0, 1) if k else (0,))]
+TUNINGS = [dict(kernel=k, block=b, nontemporal=nt, rows=0) for k in (0, 1)
+           for b in (64, 128, 256, 512) for nt in ((0, 1) if k else (0,))]
+TUNINGS += [dict(kernel=2, block=b, nontemporal=0, rows=r) for b in (64, 128, 256)
+            for r in (16, 32, 64)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("nx,ny", [(256, 40), (136, 9), (2, 5), (8, 3)])
-def test_every_tuning_bitwise_identical(storage, nx, ny):
+@pytest.mark.parametrize("nx,ny,steps", [(256, 40, 20), (136, 9, 21), (2, 5, 20), (8, 3, 21),
+                                         (61, 70, 20), (300, 77, 21)])
+def test_every_tuning_bitwise_identical(storage, nx, ny, steps):
     """All launch shapes run the same per-cell arithmetic: bit-identical state,
-    including the vector kernel's periodic wrap lanes and ragged tails."""
-    say("case: tunings", storage, nx, ny)
+    including the vector kernel's periodic wrap lanes and ragged tails, and
+    the two-steps-per-launch strips (chunk edges, partial strips, an odd
+    final step)."""
+    say("case: tunings", storage, nx, ny, steps)
     rho, ux, uy, chi = random_case(nx, ny, 31 + nx)
     q = (1.0, 0.04, 0.0)
     states = []
@@ -354,16 +359,16 @@ def test_every_tuning_bitwise_identical(storage, nx, ny):
                           ux_base=0.04, f16_scale=1e-3)
         lat.set_sponge(chi, q)
         lat.set_tuning(**t)
-        lat.step(20)
+        lat.step(steps)
         states.append(lat.save_state())
         lat.close()
-    for st in states[1:]:
-        np.testing.assert_array_equal(st, states[0])
-    ref = oracle.step(oracle.feq_field(rho, ux, uy), 20, chi=chi, qref=q, variant="II")
+    for t, st in zip(TUNINGS[1:], states[1:]):
+        assert (st == states[0]).all(), t
+    ref = oracle.step(oracle.feq_field(rho, ux, uy), steps, chi=chi, qref=q, variant="II")
     lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant="II", ux_base=0.04,
                       f16_scale=1e-3)
     lat.set_sponge(chi, q)
-    lat.step(20)
+    lat.step(steps)
     got = lat.populations()
     lat.close()
     if storage == "f64":
