@@ -63,17 +63,19 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
     cx, cy = spec.chi_1d()
     lat.set_sponge_separable(cx, cy, "max", spec.qref)
     tuning, tune_ms = lat.autotune(reps=10)
+    per = 2 if tuning["kernel"] == 2 else 1  # time steps per launch
+    launches = steps // per
     diag = torch.empty(7, dtype=torch.float64, device="cuda")
-    lat.step(warmup)
+    lat.step(warmup - warmup % per)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
     diag_after = set()
     t0 = time.perf_counter()
     ev[0].record(stream)
-    for i in range(steps):
-        lat.step(1)
+    for i in range(launches):
+        lat.step(per)
         ev[i + 1].record(stream)
-        if diag_every and (i + 1) % diag_every == 0:
+        if diag_every and ((i + 1) * per) % diag_every == 0:
             lbm.lbm_diagnostics_dev(lat.h, diag)
             diag_after.add(i + 1)
     torch.cuda.synchronize()
@@ -81,7 +83,7 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
     # per-launch durations of the step kernel alone (intervals that contain a
     # diagnostics launch are left out)
     durs = []
-    for i in range(steps):
+    for i in range(launches):
         if i in diag_after:
             continue
         durs.append(ev[i].elapsed_time(ev[i + 1]))
@@ -89,8 +91,9 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
     lat.close()
     wall = t1 - t0
     cells = spec.nx * spec.ny
-    return dict(wall_s=wall, ms_per_step=1e3 * wall / steps,
-                mlups=cells * steps / wall / 1e6,
+    done = launches * per
+    return dict(wall_s=wall, ms_per_step=1e3 * wall / done, steps=done,
+                mlups=cells * done / wall / 1e6, steps_per_launch=per,
                 kernel_ms=sum(durs) / len(durs), diag=[float(x) for x in d], tuning=tuning)
 
 
@@ -258,6 +261,41 @@ def precision_leg(lbm, wl, n=2048, steps=4000, chis=(0.05, 0.2, 0.5), width=48):
     return out
 
 
+def paper_pulse_leg(lbm, wl, steps=1200, every=20):
+    """The comparison of Section 4.1: E_L2(t) for no layer, the viscosity
+    ramp and the Type II layer (thickness 2b, 3b, 4b; mean flow 0 and 0.1),
+    and the log-log decay slope of E_L2 after the pulse enters the layer."""
+    import numpy as np
+    out = {}
+    for u0 in (0.0, 0.1):
+        for m in (2, 3, 4):
+            for strategy in ("none", "visc", "II"):
+                if strategy == "none" and m != 4:
+                    continue
+                spec, px, py = wl.paper_pulse(strategy, thickness_b=m, u0=u0)
+                rho, ux, uy = spec.fields()
+                lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage="f64",
+                                  variant=spec.variant, s=spec.s, ux_base=u0)
+                lat.set_sponge_separable(px, py, "max", spec.qref)
+                ts, es = [], []
+                for k in range(steps // every):
+                    lat.step(every)
+                    d = lat.diagnostics()
+                    ts.append((k + 1) * every)
+                    es.append(math.sqrt(d[3] / (spec.nx * spec.ny)))
+                lat.close()
+                ts, es = np.array(ts, float), np.array(es)
+                # the pulse front reaches the layer at (n/2 - W - 2b)/c_s steps
+                t_in = (spec.nx / 2 - spec.width - 20) / wl.CS
+                sel = (ts > 1.5 * t_in) & (es > 0)
+                slope = float(np.polyfit(np.log(ts[sel]), np.log(es[sel]), 1)[0]) if sel.sum() > 3 else None
+                out["u0=%g,%db,%s" % (u0, m, strategy)] = {
+                    "E_L2_final": float(es[-1]), "E_L2_at": {int(t): float(e) for t, e in
+                                                             zip(ts[4::10], es[4::10])},
+                    "loglog_slope": slope}
+    return out
+
+
 def cpu_baseline(spec, fields, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -290,6 +328,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-pulse", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -320,6 +359,8 @@ def main():
         print("bench: timing Type %s, %d steps" % (v, k), file=sys.stderr, flush=True)
         results[v] = time_variant(lbm, wl, torch, sv, fields, k, args.warmup)
     r = results[head]
+    # one launch reads and writes every stored element once, whether it
+    # advances one step or two
     achieved = bytes_per_cell * cells / (r["kernel_ms"] * 1e-3) / 1e9
     copy_gbps = None if args.no_copy else copy_bandwidth(lbm, torch)
 
@@ -328,7 +369,7 @@ def main():
         "value": r["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r["steps"],
         "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
@@ -346,8 +387,11 @@ def main():
                      "traffic": counter_traffic() if args.storage == "f32" and args.n == 4096
                      and head == "II" else None,
                      "algorithmic_bytes_per_launch": bytes_per_cell * cells,
-                     "kernel_ms": r["kernel_ms"]},
+                     "steps_per_launch": r["steps_per_launch"],
+                     "kernel_ms": r["kernel_ms"],
+                     "single_step_equivalent_gbps": bytes_per_cell * r["mlups"] / 1e3},
         "per_variant": {v: {"mlups": x["mlups"], "kernel_ms": x["kernel_ms"],
+                            "steps_per_launch": x["steps_per_launch"],
                             "achieved_gbps": bytes_per_cell * cells / (x["kernel_ms"] * 1e-3) / 1e9,
                             "nonfinite_cells": x["diag"][6], "max_dev": x["diag"][5],
                             "tuning": x["tuning"]}
@@ -362,6 +406,9 @@ def main():
     if not args.no_precision:
         print("bench: precision study 2048^2, 4000 steps", file=sys.stderr, flush=True)
         out["precision"] = precision_leg(lbm, wl)
+    if not args.no_pulse:
+        print("bench: the paper's pulse comparison", file=sys.stderr, flush=True)
+        out["paper_pulse"] = paper_pulse_leg(lbm, wl)
     if not args.no_serve:
         out["served"] = serving_leg(torch, count=args.serve_requests,
                                     warmup=args.serve_requests // 10)

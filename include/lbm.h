@@ -56,6 +56,10 @@ extern "C" {
 #define LBM_VARIANT_I 1    /* f^ref = f^eq(q_ref), f* = f (Sec. 2.2.1)     */
 #define LBM_VARIANT_II 2   /* f^ref = f^eq(q_ref), f* = f^eq(rho*,u*) (2.2.2) */
 #define LBM_VARIANT_III 3  /* f^ref = f^L(q_ref), f* = f^L(rho*,u*) (2.2.3) */
+#define LBM_VARIANT_VISC 4 /* comparison strategy of Sec. 4.1: no damping
+                              term; the non-conserved rates ramp linearly to
+                              1 in the layer, s_k + (1 - s_k) xi, where the
+                              sponge arrays hold xi in [0, 1] instead of chi */
 
 /* ---- separable sponge combination ------------------------------------ */
 #define LBM_COMBINE_MAX 0 /* chi(x,y) = max(chi_x[x], chi_y[y]) */

@@ -29,7 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-VARIANTS = {"none": 0, "I": 1, "II": 2, "III": 3, "I_rewritten": 4}
+VARIANTS = {"none": 0, "I": 1, "II": 2, "III": 3, "I_rewritten": 4, "visc": 5}
 
 # Default relaxation rates: s = 1.9 is the only value stated in prose for the
 # Von Neumann study (Section 3.3); MRT keeps S(0..2) = 0 (Section 2.1).

@@ -138,7 +138,11 @@ static void flin(double rho, double jx, double jy, double *out) {
     out[i] = W[i] * (rho + 3.0 * (CX[i] * jx + CY[i] * jy));
 }
 
-enum { V_NONE = 0, V_I = 1, V_II = 2, V_III = 3, V_I_REWRITTEN = 4 };
+/* V_VISC: the comparison strategy of Section 4.1 (no damping term; the
+ * relaxation rates of the non-conserved moments decrease linearly towards 1
+ * inside the layer): the chi argument then carries the ramp coordinate
+ * xi in [0, 1], and s_k becomes s_k + (1 - s_k) xi for k >= 3. */
+enum { V_NONE = 0, V_I = 1, V_II = 2, V_III = 3, V_I_REWRITTEN = 4, V_VISC = 5 };
 
 /* Collision with the damping term at one cell.
  * fin: pre-collision populations; chi: sponge strength at the cell;
@@ -149,7 +153,8 @@ static void collide_cell(const double *fin, double chi, double rf, double uxf,
                          int variant, double *fout) {
   double mom[Q], f_eqs[Q], meqs[Q], tmp[Q], tmp2[Q], d[Q], mp[Q];
   /* without an absorbing term the force vanishes and rho* = rho, j* = j */
-  if (variant == V_NONE) chi = 0.0;
+  const double xi = chi;
+  if (variant == V_NONE || variant == V_VISC) chi = 0.0;
   matvec(M_D2Q9, fin, mom);
   const double rho = mom[0], jx = mom[1], jy = mom[2];
   const double jxf = rf * uxf, jyf = rf * uyf;
@@ -185,6 +190,9 @@ static void collide_cell(const double *fin, double chi, double rf, double uxf,
       for (int k = 0; k < Q; ++k) d[k] = chi * (a[k] - b[k]);
       break;
     }
+    case V_VISC:
+      for (int k = 3; k < Q; ++k) sk[k] = s[k] + (1.0 - s[k]) * xi;
+      break;
     case V_I_REWRITTEN: { /* eq. app:newbgka: S' = S + chi I, force F */
       double a[Q];
       feq(rf, jxf, jyf, tmp);
@@ -216,7 +224,8 @@ static inline int64_t wrap(int64_t a, int64_t n) {
  *   s      : 9 relaxation rates (diagonal of S).
  *   srel   : [ny][nx] per-cell rate replacing s[3..8], or NULL.
  *   n, m   : shift parameters (0.5 in the paper).
- *   variant: 0 none, 1 Type I, 2 Type II, 3 Type III, 4 Type I rewritten.
+ *   variant: 0 none, 1 Type I, 2 Type II, 3 Type III, 4 Type I rewritten,
+ *            5 viscosity ramp (chi then holds the ramp coordinate xi).
  *   nthreads: OpenMP threads (<= 0: library default).
  * Returns 0, or -1 on bad arguments.
  */

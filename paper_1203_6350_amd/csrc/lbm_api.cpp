@@ -97,7 +97,7 @@ int validate_config(const lbm_config *c) {
     return fail(LBM_EINVAL, "shift parameters must be finite and >= 0");
   if (c->storage < LBM_STORAGE_F64 || c->storage > LBM_STORAGE_F16)
     return fail(LBM_EINVAL, "unknown storage mode");
-  if (c->variant < LBM_VARIANT_NONE || c->variant > LBM_VARIANT_III)
+  if (c->variant < LBM_VARIANT_NONE || c->variant > LBM_VARIANT_VISC)
     return fail(LBM_EINVAL, "unknown damping variant");
   if (c->storage == LBM_STORAGE_F16 && !(c->f16_scale > 0 && is_fin(c->f16_scale)))
     return fail(LBM_EINVAL, "f16_scale must be finite and > 0");
@@ -179,11 +179,14 @@ int check_qref(const lbm_qref *q) {
   return LBM_OK;
 }
 
-int check_chi(const double *a, size_t n) {
+int check_chi(const double *a, size_t n, int variant) {
   if (!a) return LBM_OK;
-  for (size_t i = 0; i < n; ++i)
+  for (size_t i = 0; i < n; ++i) {
     if (!(a[i] >= 0.0) || !is_fin(a[i]))
       return fail(LBM_EINVAL, "chi must be finite and >= 0");
+    if (variant == LBM_VARIANT_VISC && a[i] > 1.0)
+      return fail(LBM_EINVAL, "the viscosity ramp coordinate must lie in [0, 1]");
+  }
   return LBM_OK;
 }
 
@@ -312,7 +315,7 @@ int lbm_set_sponge(lbm_handle *h, const double *chi, const lbm_qref *q) {
   int rc = check_qref(q);
   if (rc) return rc;
   const size_t N = (size_t)(h->user.nx * h->user.ny);
-  rc = check_chi(chi, N);
+  rc = check_chi(chi, N, h->user.variant);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   free_sponge(h);
@@ -341,8 +344,8 @@ int lbm_set_sponge_separable(lbm_handle *h, const double *chi_x,
     return fail(LBM_EINVAL, "unknown combine mode");
   int rc = check_qref(q);
   if (rc) return rc;
-  rc = check_chi(chi_x, (size_t)h->user.nx);
-  if (!rc) rc = check_chi(chi_y, (size_t)h->user.ny);
+  rc = check_chi(chi_x, (size_t)h->user.nx, h->user.variant);
+  if (!rc) rc = check_chi(chi_y, (size_t)h->user.ny, h->user.variant);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   free_sponge(h);

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(BX) void batch_step_kernel(
       case V_I: collide<C, V_I>(g, chi, p); break;
       case V_II: collide<C, V_II>(g, chi, p); break;
       case V_III: collide<C, V_III>(g, chi, p); break;
+      case V_VISC: collide<C, V_VISC>(g, chi, p); break;
       default: collide<C, V_NONE>(g, chi, p); break;
     }
 #pragma unroll

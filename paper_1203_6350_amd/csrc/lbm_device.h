@@ -41,7 +41,11 @@
 
 namespace lbm {
 
-enum Variant { V_NONE = 0, V_I = 1, V_II = 2, V_III = 3 };
+// V_VISC is the comparison strategy of Section 4.1: no damping term; the
+// non-conserved relaxation rates ramp linearly to 1 inside the layer,
+// s_k(x) = s_k + (1 - s_k) xi(x), with xi in [0, 1] supplied where the other
+// variants take chi.
+enum Variant { V_NONE = 0, V_I = 1, V_II = 2, V_III = 3, V_VISC = 4 };
 enum ChiMode { CHI_ZERO = 0, CHI_FIELD = 1, CHI_SEP_MAX = 2, CHI_SEP_SUM = 3 };
 
 // Velocity set in the column order of M (Appendix A.1).
@@ -137,7 +141,7 @@ __device__ __forceinline__ void collide(C g[9], C chi,
 
   // ---- shifted conserved quantities dc*
   C dr = dm[0], djx = dm[1], djy = dm[2];
-  if (VAR != V_NONE) {
+  if (VAR != V_NONE && VAR != V_VISC) {
     const C nchi = p.n * chi, mchi = p.m * chi;
     const C inv_n = recip(C(1) + nchi);
     const C inv_m = p.n == p.m ? inv_n : recip(C(1) + mchi);
@@ -173,8 +177,10 @@ __device__ __forceinline__ void collide(C g[9], C chi,
   C mp[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    mp[k] = fmaC(p.s[k], meq[k] - dm[k], dm[k]);
-    if (VAR != V_NONE) mp[k] = mp[k] + d[k];
+    C sk = p.s[k];
+    if (VAR == V_VISC && k >= 3) sk = fmaC(C(1) - sk, chi, sk);
+    mp[k] = fmaC(sk, meq[k] - dm[k], dm[k]);
+    if (VAR != V_NONE && VAR != V_VISC) mp[k] = mp[k] + d[k];
   }
 
   // ---- g' = M^-1 dm'

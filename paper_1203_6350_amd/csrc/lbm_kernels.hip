@@ -472,6 +472,7 @@ static hipError_t dispatch_var(const StepConfig &c, const void *src, void *dst,
     case V_I: return dispatch_chi<S, V_I>(c, src, dst, s, two);
     case V_II: return dispatch_chi<S, V_II>(c, src, dst, s, two);
     case V_III: return dispatch_chi<S, V_III>(c, src, dst, s, two);
+    case V_VISC: return dispatch_chi<S, V_VISC>(c, src, dst, s, two);
   }
   return hipErrorInvalidValue;
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
-VARIANT = {"none": 0, "I": 1, "II": 2, "III": 3}
+VARIANT = {"none": 0, "I": 1, "II": 2, "III": 3, "visc": 4}
 COMBINE = {"max": 0, "sum": 1}
 _CODE_NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTABLE", -5: "ESTATE"}
 

@@ -190,6 +190,29 @@ def large_c2(variant="II", storage="f32", steps=2000, n=4096, base="ref") -> Dom
                       seed=SEED_BASE + 1)
 
 
+def paper_pulse(strategy="II", thickness_b=4, u0=0.0, s=1.9999, n=200, b_cells=10.0,
+                storage="f64"):
+    """The pulse of Section 4.1 on an n x n lattice: eps = 1e-3, b = n/20 cells,
+    centred; absorbing layer of thickness m b on all sides. Type II uses
+    chi = 4/s - 0.001 with the normalised A = n = 4 profile of eq.
+    normalizedsigma (sigma = chi sigma~); the viscosity strategy ramps the
+    rates linearly to 1 over the same layer (its sponge arrays carry the ramp
+    coordinate xi); 'none' has no layer. Returns (spec, profile_x, profile_y)."""
+    W = int(round(thickness_b * b_cells))
+    c = (n - 1) / 2
+    S = (0.0, 0.0, 0.0) + (s,) * 6
+    spec = DomainSpec(nx=n, ny=n, variant={"none": "none", "visc": "visc"}.get(strategy, strategy),
+                      storage=storage, s=S, chi_max=4.0 / s - 0.001, width=W, u0=u0,
+                      pulses=[(c, c, 1e-3, b_cells)])
+    if strategy == "none":
+        prof = np.zeros(n)
+    elif strategy == "visc":
+        prof = ramp_depth(n, W)
+    else:
+        prof = orszag_profile_1d(n, W, spec.chi_max)
+    return spec, prof, prof.copy()
+
+
 def batch_c4(count=256, seed_index=3, max_exp=1.0):
     """Uneven domains N = round(64 * 8^U), U ~ U[0, max_exp]; chi_max U[0.01, 0.5];
     W U{8..64} clamped to N/4; Mach U[0, 0.3]; variant U{I, II, III};

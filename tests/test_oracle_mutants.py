@@ -34,7 +34,8 @@ MUTANTS = {
     "weights_swapped": ("static const double W[Q] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,\n                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};",
                         "static const double W[Q] = {4.0 / 9,  1.0 / 36,  1.0 / 9,  1.0 / 9, 1.0 / 9,\n                            1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36};"),
     "velocity_from_wrong_row": ("CY[j] = (int)M_D2Q9[2][j];", "CY[j] = (int)M_D2Q9[6][j] / -2;"),
-    "none_keeps_shift": ("if (variant == V_NONE) chi = 0.0;", ""),
+    "none_keeps_shift": ("if (variant == V_NONE || variant == V_VISC) chi = 0.0;", "if (variant == V_VISC) chi = 0.0;"),
+    "visc_ramp_wrong_end": ("sk[k] = s[k] + (1.0 - s[k]) * xi;", "sk[k] = s[k] + (2.0 - s[k]) * xi;"),
 }
 
 

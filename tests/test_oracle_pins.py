@@ -422,3 +422,33 @@ def test_multi_step_mode_evolution():
         lin = (up - dn) / (2 * eps)
         coef = (lin * np.conj(phase)[None]).sum(axis=(1, 2)) / (nx * ny / 2)
         np.testing.assert_allclose(coef, lam[i] ** T * vec[:, i], rtol=0, atol=1e-7)
+
+
+# ------------------------------------------------------------------ viscosity-ramp strategy (Sec. 4.1)
+
+def test_viscosity_ramp_limits():
+    """The comparison strategy of Section 4.1 (rates ramped linearly to 1 in
+    the layer): at xi = 0 it is the plain scheme bit for bit; at xi = 1 every
+    non-conserved moment relaxes fully, so one collision lands exactly on
+    f^eq(rho, j) (the BGK s = 1 limit); in between, a uniform state keeps its
+    conserved moments and its non-conserved moments relax by 1 - s'."""
+    f = random_state(12, 10, 41)
+    S = (0.0, 0.0, 0.0, 1.5, 1.6, 1.7, 1.8, 1.9, 1.95)
+    a = oracle.step(f, 7, s=S, chi=0.0, variant="visc")
+    b = oracle.step(f, 7, s=S, chi=0.0, variant="none")
+    np.testing.assert_array_equal(a, b)
+    M, *_ = oracle.tables()
+    fin = f[:, 0, :].T
+    out = oracle.collide(fin, s=S, chi=1.0, variant="visc")
+    mom = fin @ M.T
+    expect = oracle.feq_field(mom[:, 0], mom[:, 1] / mom[:, 0], mom[:, 2] / mom[:, 0]).T
+    np.testing.assert_allclose(out, expect, rtol=0, atol=1e-15)
+    xi = 0.3
+    out = oracle.collide(fin, s=S, chi=xi, variant="visc")
+    m_in, m_out = fin @ M.T, out @ M.T
+    meq = oracle.feq_field(m_in[:, 0], m_in[:, 1] / m_in[:, 0], m_in[:, 2] / m_in[:, 0]).T @ M.T
+    np.testing.assert_allclose(m_out[:, :3], m_in[:, :3], rtol=0, atol=1e-15)
+    for k in range(3, 9):
+        sk = S[k] + (1 - S[k]) * xi
+        np.testing.assert_allclose(m_out[:, k] - meq[:, k], (1 - sk) * (m_in[:, k] - meq[:, k]),
+                                   rtol=0, atol=1e-15)
