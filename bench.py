@@ -41,20 +41,22 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic():
-    """HBM bytes per step launch from the committed rocprofv3 --pmc summary,
-    or None when the kernel source changed since the counters were taken."""
+def counter_traffic(tuning):
+    """HBM bytes per launch of the given launch shape from the committed
+    rocprofv3 --pmc summary, or None when the kernel source changed since the
+    counters were taken or that shape was not profiled."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     txt = open(PMC_SUMMARY).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    b = re.search(r"scaled_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    key = "%d,%d,%d" % (tuning["kernel"], tuning["block"], tuning.get("rows", 0) if tuning["kernel"] == 2 else 0)
+    b = re.search(r"scaled_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != kernel_hash():
         return None
     return float(b.group(1))
 
 
-def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
+def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100, fixed=None):
     rho, ux, uy = fields
     stream = torch.cuda.current_stream()
     lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage=spec.storage,
@@ -62,7 +64,11 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100):
                       f16_scale=5e-4, stream=stream)
     cx, cy = spec.chi_1d()
     lat.set_sponge_separable(cx, cy, "max", spec.qref)
-    tuning, tune_ms = lat.autotune(reps=10)
+    if fixed is None:
+        tuning, tune_ms = lat.autotune(reps=10)
+    else:
+        lat.set_tuning(**fixed)
+        tuning = lat.tuning()
     per = 2 if tuning["kernel"] == 2 else 1  # time steps per launch
     launches = steps // per
     diag = torch.empty(7, dtype=torch.float64, device="cuda")
@@ -329,6 +335,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-pulse", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="kernel,block,rows: fixed launch shape instead of the autotuner "
+                         "(for profiling runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -357,7 +366,11 @@ def main():
         sv = wl.large_c2(variant=v, storage=args.storage, n=args.n)
         k = args.steps if v == head else max(100, args.steps // 4)
         print("bench: timing Type %s, %d steps" % (v, k), file=sys.stderr, flush=True)
-        results[v] = time_variant(lbm, wl, torch, sv, fields, k, args.warmup)
+        fixed = None
+        if args.tuning:
+            kk, bb, rr = (int(x) for x in args.tuning.split(","))
+            fixed = dict(kernel=kk, block=bb, rows=rr)
+        results[v] = time_variant(lbm, wl, torch, sv, fields, k, args.warmup, fixed=fixed)
     r = results[head]
     # one launch reads and writes every stored element once, whether it
     # advances one step or two
@@ -384,8 +397,8 @@ def main():
                    "diagnostics_every": 100},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS,
-                     "traffic": counter_traffic() if args.storage == "f32" and args.n == 4096
-                     and head == "II" else None,
+                     "traffic": counter_traffic(r["tuning"]) if args.storage == "f32"
+                     and args.n == 4096 and head == "II" else None,
                      "algorithmic_bytes_per_launch": bytes_per_cell * cells,
                      "steps_per_launch": r["steps_per_launch"],
                      "kernel_ms": r["kernel_ms"],
