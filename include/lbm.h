@@ -197,13 +197,15 @@ typedef struct lbm_tuning {
                           (4 cells FP32, 2 FP64, 8 FP16; needs nx % cells == 0,
                           otherwise the library falls back to 0);
                           2: two time steps per launch (each 64-lane wave
-                          owns a 60-column strip of a chunk of rows and
-                          reads/writes the lattice once per two steps; an
-                          odd remaining step uses kernel 0)                  */
-  int32_t block;       /* threads per block: 64, 128, 256 or 512 (kernel 2:
-                          64, 128 or 256)                                   */
+                          owns a 60-column strip of a chunk of rows, the
+                          block's waves take adjacent strips; the lattice is
+                          read and written once per two steps; an odd
+                          remaining step uses kernel 0)                      */
+  int32_t block;       /* threads per block: 64, 128, 256 or 512            */
   int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
-  int32_t rows;        /* kernel 2: rows per chunk (16..1024), else ignored  */
+  int32_t rows;        /* kernel 2: rows per chunk, 1..4096, or 0 for the
+                          height at which all blocks are resident at once;
+                          ignored by kernels 0 and 1                        */
 } lbm_tuning;
 
 int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t);

@@ -512,9 +512,9 @@ int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t) {
   if (t->kernel < 0 || t->kernel > 2) return fail(LBM_EINVAL, "kernel must be 0, 1 or 2");
   if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
     return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512");
-  if (t->kernel == 2 && t->block == 512) return fail(LBM_EINVAL, "kernel 2 takes block 64, 128 or 256");
   if (t->nontemporal != 0 && t->nontemporal != 1) return fail(LBM_EINVAL, "nontemporal must be 0 or 1");
-  if (t->kernel == 2 && (t->rows < 16 || t->rows > 1024)) return fail(LBM_EINVAL, "rows must be 16..1024");
+  if (t->kernel == 2 && (t->rows < 0 || t->rows > 4096))
+    return fail(LBM_EINVAL, "rows must be 0 (fit the device) or 1..4096");
   h->cfg.kernel = t->kernel;
   h->cfg.block = t->block;
   h->cfg.nontemporal = t->kernel == 1 ? t->nontemporal : 0;
@@ -543,8 +543,8 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
   if (lbm::vec_supported(h->cfg))
     for (int nt = 0; nt < 2; ++nt)
       for (int b : blocks) cands.push_back(lbm_tuning{1, b, nt, 0});
-  const int rows[4] = {16, 32, 48, 64};
-  for (int b = 64; b <= 256; b *= 2)
+  const int rows[4] = {0, 8, 16, 32};
+  for (int b : blocks)
     for (int r : rows) cands.push_back(lbm_tuning{2, b, 0, r});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");

@@ -19,7 +19,8 @@
 //   d        = chi (dm^ref - dm)          Type I   (f* = f)
 //              chi (dm^ref - dm^eq*)      Type II  (f* = f^eq(rho*, u*))
 //              chi L (dc^f - dc*)         Type III (f* = f^L(rho*, u*))
-//   dm'      = dm + S o (dm^eq* - dm) + d (Lambda = M^-1 S M, Gamma = chi I)
+//   dm'      = dm + S o (dm^eq* - dm) + d (Lambda = M^-1 S M, Gamma = chi I;
+//                                         d enters as fma(chi, e, .))
 //   g'       = M^-1 dm' = M^T diag(1/9,1/6,1/6,1/36,1/36,1/12,1/12,1/4,1/4) dm'
 //
 // m^eq(rho, j) = (rho, jx, jy, -2 rho + 3|j|^2/rho, rho - 3|j|^2/rho, -jx, -jy,
@@ -116,11 +117,20 @@ __device__ __forceinline__ void meq_delta(C dr, C djx, C djy, C rho_b, C ubx,
   out[8] = qxy;
 }
 
+// Reference moments dm^ref = m^eq(c^f) - m^eq(c_b) of the damping Types I
+// and II. They depend on the launch parameters only, so a kernel that
+// collides many cells per thread computes them once.
+template <typename C>
+__device__ __forceinline__ void ref_moments(const CollideParams<C> &p, C mref[9]) {
+  meq_delta(p.dcf0, p.dcf1, p.dcf2, p.rho_b, p.ubx, p.uby, mref);
+}
+
 // One collision in deviation form; g holds the pre-collision deviations on
-// entry and the post-collision deviations on return.
+// entry and the post-collision deviations on return. mref comes from
+// ref_moments (read by Types I and II only).
 template <typename C, int VAR>
-__device__ __forceinline__ void collide(C g[9], C chi,
-                                        const CollideParams<C> &p) {
+__device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p,
+                                        const C mref[9]) {
   // ---- dm = M g (Appendix A.1)
   const C ax = g[1] + g[3], ay = g[2] + g[4];
   const C sa = ax + ay;                     // axis populations
@@ -154,33 +164,29 @@ __device__ __forceinline__ void collide(C g[9], C chi,
   C meq[9];
   meq_delta(dr, djx, djy, p.rho_b, p.ubx, p.uby, meq);
 
-  // ---- damping d (Gamma = chi I) and relaxation
-  C d[9];
-  if (VAR == V_I || VAR == V_II) {
-    C mref[9];
-    meq_delta(p.dcf0, p.dcf1, p.dcf2, p.rho_b, p.ubx, p.uby, mref);
-#pragma unroll
-    for (int k = 0; k < 9; ++k)
-      d[k] = chi * (mref[k] - (VAR == V_I ? dm[k] : meq[k]));
-  } else if (VAR == V_III) {
-    const C a = p.dcf0 - dr, bx = p.dcf1 - djx, by = p.dcf2 - djy;
-    d[0] = chi * a;
-    d[1] = chi * bx;
-    d[2] = chi * by;
-    d[3] = chi * (C(-2) * a);
-    d[4] = chi * a;
-    d[5] = chi * (-bx);
-    d[6] = chi * (-by);
-    d[7] = C(0);
-    d[8] = C(0);
-  }
+  // ---- relaxation, then the damping d = chi e (Gamma = chi I) added with
+  // one fused multiply-add per moment
   C mp[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     C sk = p.s[k];
     if (VAR == V_VISC && k >= 3) sk = fmaC(C(1) - sk, chi, sk);
     mp[k] = fmaC(sk, meq[k] - dm[k], dm[k]);
-    if (VAR != V_NONE && VAR != V_VISC) mp[k] = mp[k] + d[k];
+  }
+  if (VAR == V_I || VAR == V_II) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      mp[k] = fmaC(chi, mref[k] - (VAR == V_I ? dm[k] : meq[k]), mp[k]);
+  } else if (VAR == V_III) {
+    // e = L (dc^f - dc*), L c = (rho, jx, jy, -2 rho, rho, -jx, -jy, 0, 0)
+    const C a = p.dcf0 - dr, bx = p.dcf1 - djx, by = p.dcf2 - djy;
+    mp[0] = fmaC(chi, a, mp[0]);
+    mp[1] = fmaC(chi, bx, mp[1]);
+    mp[2] = fmaC(chi, by, mp[2]);
+    mp[3] = fmaC(chi, C(-2) * a, mp[3]);
+    mp[4] = fmaC(chi, a, mp[4]);
+    mp[5] = fmaC(chi, -bx, mp[5]);
+    mp[6] = fmaC(chi, -by, mp[6]);
   }
 
   // ---- g' = M^-1 dm'
@@ -202,6 +208,14 @@ __device__ __forceinline__ void collide(C g[9], C chi,
   g[6] = (pd - bx) + (by - a8);
   g[7] = (pd - bx) - (by - a8);
   g[8] = (pd + bx) - (by + a8);
+}
+
+// The same collision for a thread that collides one cell.
+template <typename C, int VAR>
+__device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p) {
+  C mref[9];
+  if (VAR == V_I || VAR == V_II) ref_moments(p, mref);
+  collide<C, VAR>(g, chi, p, mref);
 }
 
 // Storage traits: load/store one population element with the per-direction

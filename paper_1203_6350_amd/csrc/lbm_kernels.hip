@@ -10,6 +10,7 @@
 // coalesced and the reads of the six x-shifted planes are offset by one
 // element.
 #include <cmath>
+#include <type_traits>
 
 #include "lbm_device.h"
 #include "lbm_internal.h"
@@ -209,14 +210,22 @@ __global__ __launch_bounds__(BX) void step_vec(
 // plus two halo columns on each side. The wave marches down the rows. When
 // row a of the input lattice A arrives, the lanes compute the first step at
 // row a - 1 and the second step at row a - 2. Pulls along x come from the
-// neighbouring lanes (shuffles); pulls along y come from carried registers:
-// each row's nine populations are used by three consecutive rows, three by
-// each (c_y = -1 now, c_y = 0 one row later, c_y = +1 two rows later), so nine
-// carried values per step suffice. A lane's first-step result is valid on
-// lanes 1..62 and its second-step result on lanes 2..61, the strip's outputs.
+// neighbouring lanes (DPP wave shifts); pulls along y from registers carried
+// over rows. A row's populations are consumed in three groups, each by one
+// first step: {4, 7, 8} (c_y = -1) by the step at the row above, {0, 1, 3}
+// (c_y = 0) by the step at the row itself, {2, 5, 6} (c_y = +1) by the step
+// at the row below. The same holds for the first-step results feeding the
+// second step. A lane's first-step result is valid on lanes 1..62 and its
+// second-step result on lanes 2..61, the strip's outputs.
+//
 // The first-step result is rounded through the storage format before the
 // second step reads it, exactly as a stored and reloaded value would be, so
 // the result is bit-identical to two launches of the one-step kernels.
+//
+// Everything that indexes rows is uniform across the wave (scalar
+// registers); per lane only the column offset differs. The row loop is
+// unrolled over six phases so that each carried group keeps a fixed register
+// per phase (a ring of three or two), which leaves no register moves.
 constexpr int STRIP = 60;
 
 template <typename S>
@@ -228,33 +237,212 @@ __device__ __forceinline__ typename Store<S>::C roundtrip(typename Store<S>::C v
   return Store<S>::load(&t, scale);
 }
 
-template <typename C>
-__device__ __forceinline__ C lane_up(C v) {  // value of lane - 1
-  return __shfl_up(v, 1, 64);
+// DPP wave shifts: wave_shr:1 gives lane l the value of lane l - 1,
+// wave_shl:1 the value of lane l + 1 (lanes 0 and 63 receive 0; their
+// results are never stored).
+__device__ __forceinline__ int wave_shr1(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
 }
-template <typename C>
-__device__ __forceinline__ C lane_down(C v) {  // value of lane + 1
-  return __shfl_down(v, 1, 64);
+__device__ __forceinline__ int wave_shl1(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float lane_up(float v) {  // value of lane - 1
+  return __builtin_bit_cast(float, wave_shr1(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float lane_down(float v) {  // value of lane + 1
+  return __builtin_bit_cast(float, wave_shl1(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_up(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)wave_shr1((int)b), hi = (unsigned)wave_shr1((int)(b >> 32));
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_down(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)wave_shl1((int)b), hi = (unsigned)wave_shl1((int)(b >> 32));
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One first-or-second step at one row: rm = populations of the row above
-// (y - 1, gives c_y = +1 pulls: 2, 5, 6), r0 = this row (0, 1, 3), rp = the
-// row below (y + 1, gives 4, 7, 8). The x shifts come from the neighbours.
-template <typename C, int VAR>
-__device__ __forceinline__ void pull_collide(const C rm[9], const C r0[9], const C rp[9],
-                                             C chi, const CollideParams<C> &p, C out[9]) {
-  out[0] = r0[0];
-  out[1] = lane_up(r0[1]);
-  out[2] = rm[2];
-  out[3] = lane_down(r0[3]);
-  out[4] = rp[4];
-  out[5] = lane_up(rm[5]);
-  out[6] = lane_down(rm[6]);
-  out[7] = lane_down(rp[7]);
-  out[8] = lane_up(rp[8]);
-  collide<C, VAR>(out, chi, p);
-}
+// Carried state of one wave. Ring slots are indexed by the row's position
+// q = row - Y0 + 2 within the chunk (q >= 0): a group live over two
+// iterations sits in slot q % 2, one live over three in slot q % 3.
+template <typename C>
+struct StripState {
+  C a478[3][3];  // A rows: populations 4, 7, 8 (loaded two rows ahead)
+  C a013[3][3];  // A rows: populations 0, 1, 3
+  C a256[3][3];  // A rows: populations 2, 5, 6
+  C achi[3];     // sponge input (chi_raw) of A rows
+  C b013[2][3];  // first-step rows: populations 0, 1, 3
+  C b256[3][3];  // first-step rows: populations 2, 5, 6
+  C bchi[2];     // sponge strength of first-step rows
+};
 
+template <typename S, int VAR, int CHI, int NW>
+struct StripCtx {
+  typedef typename Store<S>::C C;
+  const S *src;
+  S *dst;
+  int64_t ps, pitch;
+  unsigned col;       // this lane's column
+  unsigned col_bytes; // col * sizeof(S)
+  unsigned out_bytes; // (lane - 2) * sizeof(S): output offset from the strip start
+  bool store_lane;
+  int nx, ny, Y0, X0;
+  C cx_chi;
+  const C *chi_field, *chiy;
+  C scale[9], inv_scale[9];
+  CollideParams<C> p;
+  C mref[9];
+
+  __device__ __forceinline__ int wrap_row(int r) const {
+    r %= ny;
+    return r < 0 ? r + ny : r;
+  }
+  // The row's address is uniform across the wave; routing it through
+  // readfirstlane keeps it in scalar registers, so the load adds only the
+  // lane's 32-bit byte offset to it (no per-lane 64-bit addresses).
+  // global-memory views: elements move as same-size integers (the FP16
+  // element type is a class, which address-space pointers do not copy)
+  typedef typename std::conditional<
+      sizeof(S) == 2, uint16_t,
+      typename std::conditional<sizeof(S) == 4, uint32_t, uint64_t>::type>::type Bits;
+  typedef __attribute__((address_space(1))) Bits GS;
+  typedef __attribute__((address_space(1))) char GChar;
+  static __device__ __forceinline__ GChar *uniform_ptr(const void *p) {
+    const uint64_t u = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (GChar *)(lo | (hi << 32));
+  }
+  // The lane's byte offset is re-materialised at each use (an empty asm
+  // that emits nothing), so the 32-bit offset reaches the load itself and
+  // the instruction takes the scalar base + 32-bit vector offset form.
+  static __device__ __forceinline__ unsigned local(unsigned v) {
+    asm volatile("" : "+v"(v));
+    return v;
+  }
+  __device__ __forceinline__ C ld(int i, int r) const {
+    const GS *q =
+        (const GS *)(uniform_ptr(src + i * ps + (int64_t)r * pitch) + local(col_bytes));
+    const Bits b = *q;
+    S v;
+    __builtin_memcpy(&v, &b, sizeof(S));
+    return Store<S>::load(&v, scale[i]);
+  }
+  // store of population i at this lane's output column of row y
+  __device__ __forceinline__ void st_out(int i, int y, C v) const {
+    GS *q = (GS *)(uniform_ptr(dst + i * ps + (int64_t)y * pitch + X0) + local(out_bytes));
+    S t;
+    Store<S>::store(&t, v, inv_scale[i]);
+    Bits b;
+    __builtin_memcpy(&b, &t, sizeof(S));
+    *q = b;
+  }
+  // Sponge input of row r: the field value at this lane, or chi_y[r] of a
+  // separable profile (combined with chi_x by chi_of when used).
+  __device__ __forceinline__ C chi_raw(int r) const {
+    if (CHI == CHI_ZERO) return C(0);
+    if (CHI == CHI_FIELD) return chi_field[(int64_t)r * pitch + col];
+    return chiy[r];
+  }
+  __device__ __forceinline__ C chi_of(C raw) const {
+    if (CHI == CHI_SEP_MAX) return cx_chi > raw ? cx_chi : raw;
+    if (CHI == CHI_SEP_SUM) return cx_chi + raw;
+    return raw;
+  }
+  // Loads of A row r (position Q).
+  template <int Q>
+  __device__ __forceinline__ void load_478(StripState<C> &st, int r) const {
+    st.a478[Q % 3][0] = ld(4, r);
+    st.a478[Q % 3][1] = ld(7, r);
+    st.a478[Q % 3][2] = ld(8, r);
+  }
+  template <int Q>
+  __device__ __forceinline__ void load_013(StripState<C> &st, int r) const {
+    st.a013[Q % 3][0] = ld(0, r);
+    st.a013[Q % 3][1] = ld(1, r);
+    st.a013[Q % 3][2] = ld(3, r);
+  }
+  template <int Q>
+  __device__ __forceinline__ void load_256(StripState<C> &st, int r) const {
+    st.a256[Q % 3][0] = ld(2, r);
+    st.a256[Q % 3][1] = ld(5, r);
+    st.a256[Q % 3][2] = ld(6, r);
+  }
+
+  // Iteration at input row a (position P): load what later steps read of
+  // rows a + 1 (periodic row index r_next) and a + 2 (r_next2, populations
+  // 4, 7, 8, which the first step needs soonest), first step at row a - 1,
+  // second step (SECOND) at row a - 2. left = iterations remaining including
+  // this one.
+  template <int P, bool SECOND>
+  __device__ __forceinline__ void iter(StripState<C> &st, int a, int r_next, int r_next2,
+                                       int left) const {
+    if (NW > 1) __builtin_amdgcn_s_barrier();  // rows of the strip group in step
+    if (left > 2) load_478<P + 2>(st, r_next2);
+    if (left > 2) load_013<P + 1>(st, r_next);
+    // first step at row a - 1 (position P - 1)
+    C g[9];
+    {
+      const C *rm = st.a256[(P + 1) % 3];  // row a - 2: slot (P - 2) % 3
+      const C *r0 = st.a013[(P + 2) % 3];  // row a - 1: slot (P - 1) % 3
+      const C *rp = st.a478[P % 3];        // row a
+      g[0] = r0[0];
+      g[1] = lane_up(r0[1]);
+      g[3] = lane_down(r0[2]);
+      g[2] = rm[0];
+      g[5] = lane_up(rm[1]);
+      g[6] = lane_down(rm[2]);
+      g[4] = rp[0];
+      g[7] = lane_down(rp[1]);
+      g[8] = lane_up(rp[2]);
+    }
+    // row a - 2's {2, 5, 6} are consumed: its slot takes row a + 1's
+    if (left > 3) load_256<P + 1>(st, r_next);
+    const C chi1 = chi_of(st.achi[(P + 2) % 3]);
+    // the sponge input of row a + 1 is read after this use, so waiting for
+    // it does not hold up this row
+    if (left > 2) st.achi[(P + 1) % 3] = chi_raw(r_next);
+    collide<C, VAR>(g, chi1, p, mref);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = roundtrip<S>(g[i], scale[i], inv_scale[i]);
+    if (SECOND) {
+      // second step at row a - 2 from first-step rows a - 3, a - 2, a - 1
+      const C *rm = st.b256[P % 3];        // row a - 3: slot (P - 3) % 3
+      const C *r0 = st.b013[P % 2];        // row a - 2: slot (P - 2) % 2
+      C o[9];
+      o[0] = r0[0];
+      o[1] = lane_up(r0[1]);
+      o[3] = lane_down(r0[2]);
+      o[2] = rm[0];
+      o[5] = lane_up(rm[1]);
+      o[6] = lane_down(rm[2]);
+      o[4] = g[4];
+      o[7] = lane_down(g[7]);
+      o[8] = lane_up(g[8]);
+      collide<C, VAR>(o, st.bchi[P % 2], p, mref);
+      if (store_lane) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_out(i, a - 2, o[i]);
+      }
+    }
+    // keep the first-step row a - 1 (position P - 1)
+    st.b013[(P + 1) % 2][0] = g[0];
+    st.b013[(P + 1) % 2][1] = g[1];
+    st.b013[(P + 1) % 2][2] = g[3];
+    st.b256[(P + 2) % 3][0] = g[2];
+    st.b256[(P + 2) % 3][1] = g[5];
+    st.b256[(P + 2) % 3][2] = g[6];
+    st.bchi[(P + 1) % 2] = chi1;
+  }
+};
+
+// A workgroup of NW waves takes NW adjacent strips of one chunk (a strip
+// group) and its waves pass a barrier at every row, so their row accesses
+// reach memory together as one contiguous run of NW * 60 elements per plane.
+// Strips past the right edge (the last group of a row of groups) repeat the
+// last strip and store nothing, so every wave of a workgroup runs the same
+// number of rows and barriers.
 template <typename S, int VAR, int CHI, int NW>
 __global__ __launch_bounds__(64 * NW) void step2_strip(
     const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
@@ -262,89 +450,101 @@ __global__ __launch_bounds__(64 * NW) void step2_strip(
     const typename Store<S>::C *__restrict__ chi_field,
     const typename Store<S>::C *__restrict__ chix,
     const typename Store<S>::C *__restrict__ chiy, int rows_per_chunk,
-    int nstrips, int nchunks, int wg_per_xcd, int nwg) {
+    int nstrips, int ngroups, int wg_per_xcd, int nwg) {
   typedef typename Store<S>::C C;
   // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
-  // contiguous range of work so neighbouring strips share an L2
+  // contiguous range of work (a band of chunk rows) so neighbouring strips
+  // and chunks share an L2
   const int v = (blockIdx.x & 7) * wg_per_xcd + (blockIdx.x >> 3);
   if (v >= nwg) return;
   const int lane = threadIdx.x & 63;
-  const int item = v * NW + (threadIdx.x >> 6);
-  if (item >= nstrips * nchunks) return;
-  const int chunk = item / nstrips, strip = item - chunk * nstrips;
-  const int X0 = strip * STRIP;
-  const int Y0 = chunk * rows_per_chunk;
-  const int Y1 = min(Y0 + rows_per_chunk, L.ny);
-  const int nx = L.nx, ny = L.ny;
-  int col = (X0 - 2 + lane) % nx;
-  if (col < 0) col += nx;
-  const int64_t ps = L.ps;
-  const bool store_lane = lane >= 2 && lane <= STRIP + 1 && X0 + lane - 2 < nx;
-  C cx_chi = C(0);
-  if (CHI == CHI_SEP_MAX || CHI == CHI_SEP_SUM) cx_chi = chix[col];
-
-  // carried values: A rows a-1 (all) and a-2 (2, 5, 6); B1 rows b-1, b-2 likewise
-  C a_m1[9], a_m2[9], b_m1[9], b_m2[9];
-  // periodic row indices, advanced incrementally (one wrap test per row)
-  auto wrap_row = [&](int a) {
-    int r = a % ny;
-    return r < 0 ? r + ny : r;
-  };
-  auto next_row = [&](int r) { return r + 1 == ny ? 0 : r + 1; };
-  auto load_row = [&](int r, C out[9]) {
-    const int64_t off = (int64_t)r * L.pitch + col;
+  const int chunk = v / ngroups, group = v - chunk * ngroups;
+  int strip = group * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool idle = strip >= nstrips;
+  if (idle) strip = nstrips - 1;
+  StripCtx<S, VAR, CHI, NW> c;
+  c.src = src;
+  c.dst = dst;
+  c.ps = L.ps;
+  c.pitch = L.pitch;
+  c.nx = L.nx;
+  c.ny = L.ny;
+  c.X0 = strip * STRIP;
+  c.Y0 = chunk * rows_per_chunk;
+  const int R = min(rows_per_chunk, L.ny - c.Y0);  // output rows of the chunk
+  int col = (c.X0 - 2 + lane) % L.nx;
+  if (col < 0) col += L.nx;
+  c.col = (unsigned)col;
+  c.col_bytes = (unsigned)col * (unsigned)sizeof(S);
+  c.out_bytes = (unsigned)(lane - 2) * (unsigned)sizeof(S);
+  c.store_lane = !idle && lane >= 2 && lane <= STRIP + 1 && c.X0 + lane - 2 < L.nx;
+  c.cx_chi = (CHI == CHI_SEP_MAX || CHI == CHI_SEP_SUM) ? chix[col] : C(0);
+  c.chi_field = chi_field;
+  c.chiy = chiy;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i] = Store<S>::load(src + i * ps + off, L.scale[i]);
-  };
-  auto chi_row = [&](int r) -> C {
-    if (CHI == CHI_ZERO) return C(0);
-    if (CHI == CHI_FIELD) return chi_field[(int64_t)r * L.pitch + col];
-    const C b = chiy[r];
-    if (CHI == CHI_SEP_MAX) return cx_chi > b ? cx_chi : b;
-    return cx_chi + b;
-  };
-  int r_ld = wrap_row(Y0 - 2);  // row of the load in flight (a + 1 after the top)
-  int r_m1 = wrap_row(Y0 - 3);  // row a - 1 during iteration a
-  int r_m2 = wrap_row(Y0 - 4);  // row a - 2 during iteration a
-  C nxt[9];
-  load_row(r_ld, nxt);
-  for (int a = Y0 - 2; a < Y1 + 2; ++a) {
-    C cur[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) cur[i] = nxt[i];
-    r_ld = next_row(r_ld);
-    if (a + 1 < Y1 + 2) load_row(r_ld, nxt);  // one row ahead
-    if (a >= Y0) {
-      // first step at row a - 1 from A rows a - 2, a - 1, a
-      C b[9];
-      pull_collide<C, VAR>(a_m2, a_m1, cur, chi_row(r_m1), p, b);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) b[i] = roundtrip<S>(b[i], L.scale[i], L.inv_scale[i]);
-      if (a >= Y0 + 2) {
-        // second step at row a - 2 from B1 rows a - 3, a - 2, a - 1
-        // (the first of them, Y0 - 1, exists from a = Y0 + 2 on)
-        C o[9];
-        pull_collide<C, VAR>(b_m2, b_m1, b, chi_row(r_m2), p, o);
-        if (store_lane) {
-          const int64_t off = (int64_t)(a - 2) * L.pitch + (X0 + lane - 2);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) Store<S>::store(dst + i * ps + off, o[i], L.inv_scale[i]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        b_m2[i] = b_m1[i];
-        b_m1[i] = b[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      a_m2[i] = a_m1[i];
-      a_m1[i] = cur[i];
-    }
-    r_m2 = r_m1;
-    r_m1 = next_row(r_m1);
+  for (int i = 0; i < 9; ++i) {
+    c.scale[i] = L.scale[i];
+    c.inv_scale[i] = L.inv_scale[i];
   }
+  c.p = p;
+  if (VAR == V_I || VAR == V_II) ref_moments(p, c.mref);
+
+  StripState<C> st;
+  // Positions q = 0, 1, 2 (rows Y0 - 2, Y0 - 1, Y0): the first step starts
+  // at q = 1, so row Y0 - 2 supplies only {2, 5, 6}.
+  int r = c.wrap_row(c.Y0 - 2);
+  c.template load_256<0>(st, r);
+  r = r + 1 == L.ny ? 0 : r + 1;
+  c.template load_256<1>(st, r);
+  c.template load_013<1>(st, r);
+  st.achi[1] = c.chi_raw(r);
+  r = r + 1 == L.ny ? 0 : r + 1;
+  c.template load_478<2>(st, r);
+  c.template load_013<2>(st, r);
+  c.template load_256<2>(st, r);
+  st.achi[2] = c.chi_raw(r);
+  const int r3 = r + 1 == L.ny ? 0 : r + 1;
+  c.template load_478<3>(st, r3);
+  // iterations a = Y0 .. Y0 + R + 1 (positions 2 .. R + 3)
+  auto next = [&](int rr) { return rr + 1 == L.ny ? 0 : rr + 1; };
+  int a = c.Y0;
+  int left = R + 2;
+  // positions 2 and 3: first step only (rows Y0 - 1 and Y0)
+  r = next(r);
+  c.template iter<2, false>(st, a, r, next(r), left--);
+  ++a;
+  r = next(r);
+  c.template iter<3, false>(st, a, r, next(r), left--);
+  // positions 4, 5, 0, 1, 2, 3, 4, ... (mod 6): both steps
+#define LBM_STRIP_ITER(P)                                 \
+  ++a;                                                    \
+  r = next(r);                                            \
+  c.template iter<P, true>(st, a, r, next(r), left);      \
+  if (--left == 0) break;
+  for (;;) {
+    LBM_STRIP_ITER(4)
+    LBM_STRIP_ITER(5)
+    LBM_STRIP_ITER(0)
+    LBM_STRIP_ITER(1)
+    LBM_STRIP_ITER(2)
+    LBM_STRIP_ITER(3)
+  }
+#undef LBM_STRIP_ITER
+}
+
+// Workgroups of the two-step kernel that fit on the device at once.
+template <typename S, int VAR, int CHI, int NW>
+static int64_t two_step_capacity() {
+  static const int64_t cap = [] {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step2_strip<S, VAR, CHI, NW>,
+                                                     64 * NW, 0) != hipSuccess)
+      return (int64_t)0;
+    return (int64_t)cus * per_cu;
+  }();
+  return cap;
 }
 
 template <typename S, int VAR, int CHI, int NW>
@@ -353,16 +553,22 @@ static hipError_t launch_two_t(const StepConfig &c, const void *src, void *dst,
   typedef typename Store<S>::C C;
   Lat<S> L = make_lat<S>(c);
   CollideParams<C> p = make_params<C>(c);
-  const int rows = c.rows > 0 ? c.rows : 64;
   const int nstrips = (c.nx + STRIP - 1) / STRIP;
+  const int ngroups = (nstrips + NW - 1) / NW;
+  int rows = c.rows;
+  if (rows <= 0) {
+    // chunk height that lets every workgroup be resident at once
+    const int64_t cap = two_step_capacity<S, VAR, CHI, NW>();
+    const int64_t chunks = cap > ngroups ? cap / ngroups : 1;
+    rows = (int)((c.ny + chunks - 1) / chunks);
+  }
   const int nchunks = (c.ny + rows - 1) / rows;
-  const int64_t items = (int64_t)nstrips * nchunks;
-  const int64_t nwg = (items + NW - 1) / NW;
+  const int64_t nwg = (int64_t)ngroups * nchunks;
   const int64_t per_xcd = (nwg + 7) / 8;
   if (8 * per_xcd > 0x7fffffff) return hipErrorInvalidValue;
   step2_strip<S, VAR, CHI, NW><<<dim3((unsigned)(8 * per_xcd)), dim3(64 * NW), 0, stream>>>(
       (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
-      (const C *)c.chi_y, rows, nstrips, nchunks, (int)per_xcd, (int)nwg);
+      (const C *)c.chi_y, rows, nstrips, ngroups, (int)per_xcd, (int)nwg);
   return hipGetLastError();
 }
 
@@ -372,7 +578,8 @@ static hipError_t launch_two(const StepConfig &c, const void *src, void *dst,
   switch (c.block) {
     case 64: return launch_two_t<S, VAR, CHI, 1>(c, src, dst, stream);
     case 128: return launch_two_t<S, VAR, CHI, 2>(c, src, dst, stream);
-    default: return launch_two_t<S, VAR, CHI, 4>(c, src, dst, stream);
+    case 256: return launch_two_t<S, VAR, CHI, 4>(c, src, dst, stream);
+    default: return launch_two_t<S, VAR, CHI, 8>(c, src, dst, stream);
   }
 }
 

@@ -338,8 +338,12 @@ def test_vn_paper_thresholds_on_gpu():
 
 TUNINGS = [dict(kernel=k, block=b, nontemporal=nt, rows=0) for k in (0, 1)
            for b in (64, 128, 256, 512) for nt in ((0, 1) if k else (0,))]
-TUNINGS += [dict(kernel=2, block=b, nontemporal=0, rows=r) for b in (64, 128, 256)
-            for r in (16, 32, 64)]
+# chunk heights: every remainder of the six-phase row loop (1, 5, 7, 8 = 2
+# mod 6, 16 = 4 mod 6, 48 = 0 mod 6), 0 (fitted to the device) and the
+# autotuner's candidates; blocks of 1, 2, 4 and 8 waves (strip groups whose
+# last strips are padding on every size below)
+TUNINGS += [dict(kernel=2, block=b, nontemporal=0, rows=r) for b in (64, 128, 256, 512)
+            for r in (0, 1, 5, 7, 8, 16, 32, 48)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
@@ -375,6 +379,44 @@ def test_every_tuning_bitwise_identical(storage, nx, ny, steps):
         assert rel_max(got, ref) <= 1e-12
     else:
         assert pprime_rel_l2(got, ref) <= (1e-5 if storage == "f32" else FP16_NOISE_BAR)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("variant", ["none", "I", "II", "III", "visc"])
+def test_two_step_kernel_every_variant_and_sponge_form(storage, variant):
+    """The two-steps-per-launch kernel against the one-cell-per-thread
+    kernel, bit for bit, for every damping variant and every sponge form
+    (none, 2-D field, separable max, separable sum), on a ragged size whose
+    chunks end at different phases of the row loop."""
+    nx, ny, steps = 133, 29, 9
+    say("case: two-step variants", storage, variant)
+    rho, ux, uy, chi = random_case(nx, ny, 5 + len(variant))
+    g = np.random.default_rng(8)
+    cx = g.uniform(0, 0.3, nx) * (g.uniform(size=nx) < 0.4)
+    cy = g.uniform(0, 0.3, ny) * (g.uniform(size=ny) < 0.4)
+    if variant == "I":
+        chi, cx, cy = np.minimum(chi, 0.1), np.minimum(cx, 0.05), np.minimum(cy, 0.05)
+    if variant == "visc":
+        chi, cx, cy = np.minimum(chi, 1.0), np.minimum(cx, 0.5), np.minimum(cy, 0.5)
+    q = (1.0005, 0.045, -0.003)
+    for form in ("zero", "field", "max", "sum"):
+        states = []
+        for t in (dict(kernel=0, block=64), dict(kernel=2, block=128, rows=5),
+                  dict(kernel=2, block=64, rows=4), dict(kernel=2, block=512, rows=0)):
+            lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant=variant,
+                              ux_base=0.04, f16_scale=1e-3)
+            if form == "field":
+                lat.set_sponge(chi, q)
+            elif form in ("max", "sum"):
+                lat.set_sponge_separable(cx, cy, form, q)
+            else:
+                lat.set_sponge(None, q)
+            lat.set_tuning(**t)
+            lat.step(steps)
+            states.append(lat.save_state())
+            lat.close()
+        for st in states[1:]:
+            assert (st == states[0]).all(), form
 
 
 def test_autotune_keeps_state():
