@@ -49,7 +49,7 @@ def counter_traffic(tuning):
         return None
     txt = open(PMC_SUMMARY).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    key = "%d,%d,%d" % (tuning["kernel"], tuning["block"], tuning.get("rows", 0) if tuning["kernel"] == 2 else 0)
+    key = "%d,%d,%d" % (tuning["kernel"], tuning["block"], tuning.get("rows", 0) if tuning["kernel"] >= 2 else 0)
     b = re.search(r"scaled_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != kernel_hash():
         return None
@@ -69,10 +69,10 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100, fi
     else:
         lat.set_tuning(**fixed)
         tuning = lat.tuning()
-    per = 2 if tuning["kernel"] == 2 else 1  # time steps per launch
-    launches = steps // per
+    per = tuning["kernel"] if tuning["kernel"] >= 2 else 1  # time steps per launch
+    launches, rest = divmod(steps, per)
     diag = torch.empty(7, dtype=torch.float64, device="cuda")
-    lat.step(warmup - warmup % per)
+    lat.step(warmup)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
     diag_after = set()
@@ -81,9 +81,11 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100, fi
     for i in range(launches):
         lat.step(per)
         ev[i + 1].record(stream)
-        if diag_every and ((i + 1) * per) % diag_every == 0:
+        if diag_every and (i + 1) % max(1, diag_every // per) == 0:
             lbm.lbm_diagnostics_dev(lat.h, diag)
             diag_after.add(i + 1)
+    if rest:
+        lat.step(rest)  # the remaining steps as one shorter launch, so exactly `steps` run
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # per-launch durations of the step kernel alone (intervals that contain a
@@ -97,7 +99,7 @@ def time_variant(lbm, wl, torch, spec, fields, steps, warmup, diag_every=100, fi
     lat.close()
     wall = t1 - t0
     cells = spec.nx * spec.ny
-    done = launches * per
+    done = launches * per + rest
     return dict(wall_s=wall, ms_per_step=1e3 * wall / done, steps=done,
                 mlups=cells * done / wall / 1e6, steps_per_launch=per,
                 kernel_ms=sum(durs) / len(durs), diag=[float(x) for x in d], tuning=tuning)

@@ -196,16 +196,18 @@ typedef struct lbm_tuning {
   int32_t kernel;      /* 0: one cell per thread; 1: 16-byte vector rows
                           (4 cells FP32, 2 FP64, 8 FP16; needs nx % cells == 0,
                           otherwise the library falls back to 0);
-                          2: two time steps per launch (each 64-lane wave
-                          owns a 60-column strip of a chunk of rows, the
-                          block's waves take adjacent strips; the lattice is
-                          read and written once per two steps; an odd
-                          remaining step uses kernel 0)                      */
+                          2, 3, 4: that many time steps per launch (each
+                          64-lane wave owns a strip of 64 - 2 * kernel
+                          columns of a chunk of rows, the block's waves take
+                          adjacent strips; the lattice is read and written
+                          once per launch; a shorter remainder of steps
+                          runs as one launch of that many steps, a single
+                          remaining step with kernel 0)                      */
   int32_t block;       /* threads per block: 64, 128, 256 or 512            */
   int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
-  int32_t rows;        /* kernel 2: rows per chunk, 1..4096, or 0 for the
-                          height at which all blocks are resident at once;
-                          ignored by kernels 0 and 1                        */
+  int32_t rows;        /* kernels 2-4: rows per chunk, 1..4096, or 0 for
+                          the height at which all blocks are resident at
+                          once; ignored by kernels 0 and 1                  */
 } lbm_tuning;
 
 int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t);

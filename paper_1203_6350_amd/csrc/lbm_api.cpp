@@ -369,12 +369,15 @@ int lbm_step(lbm_handle *h, int64_t n) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   int64_t k = 0;
-  if (h->cfg.kernel == lbm::KERNEL_TWO) {
-    for (; k + 2 <= n; k += 2) {
-      hipError_t e = lbm::launch_two_steps(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
-      if (e != hipSuccess) return hip_fail(e, "two-step kernel");
+  const int per = h->cfg.kernel;  // time steps per launch of the multi-step kernel
+  if (per >= lbm::KERNEL_MULTI_MIN) {
+    while (n - k >= 2) {
+      const int m = n - k >= per ? per : (int)(n - k);
+      hipError_t e = lbm::launch_multi_steps(h->cfg, m, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
+      if (e != hipSuccess) return hip_fail(e, "multi-step kernel");
       h->cur = 1 - h->cur;
-      h->steps += 2;
+      h->steps += m;
+      k += m;
     }
   }
   for (; k < n; ++k) {
@@ -509,28 +512,29 @@ int lbm_get_info(lbm_handle *h, lbm_info *info) {
 
 int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t) {
   if (!h || !t) return fail(LBM_EINVAL, "NULL argument");
-  if (t->kernel < 0 || t->kernel > 2) return fail(LBM_EINVAL, "kernel must be 0, 1 or 2");
+  if (t->kernel < 0 || t->kernel > lbm::KERNEL_MULTI_MAX)
+    return fail(LBM_EINVAL, "kernel must be 0, 1, 2, 3 or 4");
   if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
     return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512");
   if (t->nontemporal != 0 && t->nontemporal != 1) return fail(LBM_EINVAL, "nontemporal must be 0 or 1");
-  if (t->kernel == 2 && (t->rows < 0 || t->rows > 4096))
+  if (t->kernel >= 2 && (t->rows < 0 || t->rows > 4096))
     return fail(LBM_EINVAL, "rows must be 0 (fit the device) or 1..4096");
   h->cfg.kernel = t->kernel;
   h->cfg.block = t->block;
   h->cfg.nontemporal = t->kernel == 1 ? t->nontemporal : 0;
-  if (t->kernel == 2) h->cfg.rows = t->rows;
+  if (t->kernel >= 2) h->cfg.rows = t->rows;
   return LBM_OK;
 }
 
 int lbm_get_tuning(lbm_handle *h, lbm_tuning *t) {
   if (!h || !t) return fail(LBM_EINVAL, "NULL argument");
-  if (h->cfg.kernel == lbm::KERNEL_TWO)
-    t->kernel = 2;
+  if (h->cfg.kernel >= lbm::KERNEL_MULTI_MIN)
+    t->kernel = h->cfg.kernel;
   else
     t->kernel = h->cfg.kernel == lbm::KERNEL_VEC && lbm::vec_supported(h->cfg) ? 1 : 0;
   t->block = h->cfg.block;
   t->nontemporal = t->kernel == 1 ? h->cfg.nontemporal : 0;
-  t->rows = t->kernel == 2 ? h->cfg.rows : 0;
+  t->rows = t->kernel >= 2 ? h->cfg.rows : 0;
   return LBM_OK;
 }
 
@@ -544,8 +548,9 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
     for (int nt = 0; nt < 2; ++nt)
       for (int b : blocks) cands.push_back(lbm_tuning{1, b, nt, 0});
   const int rows[4] = {0, 8, 16, 32};
-  for (int b : blocks)
-    for (int r : rows) cands.push_back(lbm_tuning{2, b, 0, r});
+  for (int kk = lbm::KERNEL_MULTI_MIN; kk <= lbm::KERNEL_MULTI_MAX; ++kk)
+    for (int b : blocks)
+      for (int r : rows) cands.push_back(lbm_tuning{kk, b, 0, r});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   hipError_t e = hipEventCreate(&e1);
@@ -560,13 +565,14 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
     h->cfg.kernel = c.kernel;
     h->cfg.block = c.block;
     h->cfg.nontemporal = c.nontemporal;
-    h->cfg.rows = c.kernel == 2 ? c.rows : saved.rows;
+    h->cfg.rows = c.kernel >= 2 ? c.rows : saved.rows;
     // the candidate reads the current lattice and overwrites the other one,
     // whose contents the next step replaces anyway
     for (int k = 0; k < 2 + reps && e == hipSuccess; ++k) {
       if (k == 2) e = hipEventRecord(e0, h->stream);
       if (e == hipSuccess)
-        e = c.kernel == 2 ? lbm::launch_two_steps(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream)
+        e = c.kernel >= 2 ? lbm::launch_multi_steps(h->cfg, c.kernel, h->lat[h->cur],
+                                                    h->lat[1 - h->cur], h->stream)
                           : lbm::launch_step(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
@@ -574,7 +580,7 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) break;
-    const double per = ms / reps / (c.kernel == 2 ? 2.0 : 1.0);  // per time step
+    const double per = ms / reps / (c.kernel >= 2 ? (double)c.kernel : 1.0);  // per time step
     if (per < best_t) {
       best_t = per;
       best_c = c;
@@ -587,7 +593,7 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
   h->cfg.kernel = best_c.kernel;
   h->cfg.block = best_c.block;
   h->cfg.nontemporal = best_c.nontemporal;
-  if (best_c.kernel == 2) h->cfg.rows = best_c.rows;
+  if (best_c.kernel >= 2) h->cfg.rows = best_c.rows;
   if (best) *best = best_c;
   if (best_ms) *best_ms = best_t;
   return LBM_OK;

@@ -25,16 +25,16 @@ struct StepConfig {
   const void *chi_field; // [ny][pitch] compute type, CHI_FIELD
   const void *chi_x;     // [nx] compute type
   const void *chi_y;     // [ny] compute type
-  int kernel;            // KERNEL_GENERIC, KERNEL_VEC or KERNEL_TWO
+  int kernel;            // KERNEL_GENERIC, KERNEL_VEC, or 2..4 time steps per launch
   int block;             // threads per block: 64, 128, 256 or 512
   int nontemporal;       // 1: streaming (non-temporal) stores (vector kernel)
-  int rows;              // rows per chunk of the two-step kernel
+  int rows;              // rows per chunk of the multi-step kernel (0: fit the device)
 };
 
-enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_TWO = 2 };
-// Two time steps in one launch (src at t -> dst at t + 2).
-hipError_t launch_two_steps(const StepConfig &c, const void *src, void *dst,
-                            hipStream_t stream);
+enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MAX = 4 };
+// k = 2..4 time steps in one launch (src at t -> dst at t + k).
+hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void *dst,
+                              hipStream_t stream);
 bool vec_supported(const StepConfig &c);
 // FP16 mode: stored value = deviation / storage_scale (a power of two).
 double storage_scale(const StepConfig &c, int i);

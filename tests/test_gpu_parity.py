@@ -344,6 +344,9 @@ TUNINGS = [dict(kernel=k, block=b, nontemporal=nt, rows=0) for k in (0, 1)
 # last strips are padding on every size below)
 TUNINGS += [dict(kernel=2, block=b, nontemporal=0, rows=r) for b in (64, 128, 256, 512)
             for r in (0, 1, 5, 7, 8, 16, 32, 48)]
+# three and four steps per launch (their own halo widths and loop phases)
+TUNINGS += [dict(kernel=k, block=b, nontemporal=0, rows=r) for k in (3, 4) for b in (64, 512)
+            for r in (0, 1, 5, 8, 16, 32)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
@@ -383,13 +386,14 @@ def test_every_tuning_bitwise_identical(storage, nx, ny, steps):
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("variant", ["none", "I", "II", "III", "visc"])
-def test_two_step_kernel_every_variant_and_sponge_form(storage, variant):
-    """The two-steps-per-launch kernel against the one-cell-per-thread
-    kernel, bit for bit, for every damping variant and every sponge form
-    (none, 2-D field, separable max, separable sum), on a ragged size whose
-    chunks end at different phases of the row loop."""
+def test_multi_step_kernel_every_variant_and_sponge_form(storage, variant):
+    """The two-, three- and four-steps-per-launch kernels against the
+    one-cell-per-thread kernel, bit for bit, for every damping variant and
+    every sponge form (none, 2-D field, separable max, separable sum), on a
+    ragged size whose chunks end at different phases of the row loop (9
+    steps: whole launches plus a shorter remainder launch)."""
     nx, ny, steps = 133, 29, 9
-    say("case: two-step variants", storage, variant)
+    say("case: multi-step variants", storage, variant)
     rho, ux, uy, chi = random_case(nx, ny, 5 + len(variant))
     g = np.random.default_rng(8)
     cx = g.uniform(0, 0.3, nx) * (g.uniform(size=nx) < 0.4)
@@ -402,7 +406,8 @@ def test_two_step_kernel_every_variant_and_sponge_form(storage, variant):
     for form in ("zero", "field", "max", "sum"):
         states = []
         for t in (dict(kernel=0, block=64), dict(kernel=2, block=128, rows=5),
-                  dict(kernel=2, block=64, rows=4), dict(kernel=2, block=512, rows=0)):
+                  dict(kernel=2, block=64, rows=4), dict(kernel=2, block=512, rows=0),
+                  dict(kernel=3, block=256, rows=3), dict(kernel=4, block=128, rows=0)):
             lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant=variant,
                               ux_base=0.04, f16_scale=1e-3)
             if form == "field":
@@ -581,7 +586,8 @@ def test_full_size_4096_sampled_light_cone():
     lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage="f32", variant="II",
                       ux_base=spec.u0)
     lat.set_sponge_separable(cx, cy, "max", spec.qref)
-    lat.autotune(reps=3)
+    best, _ = lat.autotune(reps=3)
+    say("  launch shape", best)
     lat.step(T)
     r_gpu, _, _ = lat.moments()
     lat.close()
