@@ -27,15 +27,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+# FP32 (and FP64) vector FMA issue of MI355X without packed FP32 math, which
+# this library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+PEAK_VALU_TFLOPS = 78.6
+# Arithmetic of one cell update in the deviation form the kernels use (FMA =
+# 2 flop): M g (31), shifted conserved moments (13), equilibrium moments
+# (36), relaxation (27), damping term (27 for Types I and II, 18 for III),
+# the sponge value (1) and M^-1 (45); no damping and no shift without a
+# sponge term, a ramp of six rates instead for the viscosity strategy.
+FLOPS_PER_UPDATE = {"none": 139, "I": 180, "II": 180, "III": 171, "visc": 152}
 METRIC = "D2Q9 MRT+sponge MLUPS & %HBM peak; batched-served vs plain MLUPS, p99 latency"
-KERNEL_SRC = os.path.join(ROOT, "paper_1203_6350_amd", "csrc", "lbm_kernels.hip")
-DEVICE_HDR = os.path.join(ROOT, "paper_1203_6350_amd", "csrc", "lbm_device.h")
+CSRC = os.path.join(ROOT, "paper_1203_6350_amd", "csrc")
+KERNEL_SOURCES = [os.path.join(CSRC, f) for f in
+                  ("lbm_kernels.hip", "lbm_strip.h", "lbm_launch.h", "lbm_device.h")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_f32_typeII_4096_pmc.txt")
 
 
 def kernel_hash():
     h = hashlib.sha256()
-    for p in (KERNEL_SRC, DEVICE_HDR):
+    for p in KERNEL_SOURCES:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -374,10 +384,29 @@ def main():
             fixed = dict(kernel=kk, block=bb, rows=rr)
         results[v] = time_variant(lbm, wl, torch, sv, fields, k, args.warmup, fixed=fixed)
     r = results[head]
-    # one launch reads and writes every stored element once, whether it
-    # advances one step or two
-    achieved = bytes_per_cell * cells / (r["kernel_ms"] * 1e-3) / 1e9
+    # one launch reads and writes every stored element once, whatever number
+    # of time steps it advances
+    per = r["steps_per_launch"]
+    launch_s = r["kernel_ms"] * 1e-3
+    hbm_gbps = bytes_per_cell * cells / launch_s / 1e9
+    alu_tflops = FLOPS_PER_UPDATE[head] * cells * per / launch_s / 1e12
     copy_gbps = None if args.no_copy else copy_bandwidth(lbm, torch)
+    traffic = (counter_traffic(r["tuning"]) if args.storage == "f32" and args.n == 4096
+               and head == "II" else None)
+    common = {"traffic": traffic,
+              "algorithmic_bytes_per_launch": bytes_per_cell * cells,
+              "algorithmic_flops_per_launch": FLOPS_PER_UPDATE[head] * cells * per,
+              "steps_per_launch": per, "kernel_ms": r["kernel_ms"],
+              "hbm_gbps": hbm_gbps, "hbm_frac": hbm_gbps / PEAK_HBM_GBPS,
+              "alu_tflops": alu_tflops, "alu_frac": alu_tflops / PEAK_VALU_TFLOPS,
+              "single_step_equivalent_gbps": bytes_per_cell * r["mlups"] / 1e3}
+    if per >= 3:
+        # three or more steps per launch: the vector ALUs, not HBM, bound it
+        roofline = dict({"bound": "alu", "achieved": alu_tflops, "peak": PEAK_VALU_TFLOPS,
+                         "unit": "TFLOP/s", "frac": alu_tflops / PEAK_VALU_TFLOPS}, **common)
+    else:
+        roofline = dict({"bound": "hbm", "achieved": hbm_gbps, "peak": PEAK_HBM_GBPS,
+                         "unit": "GB/s", "frac": hbm_gbps / PEAK_HBM_GBPS}, **common)
 
     out = {
         "metric": METRIC,
@@ -397,14 +426,7 @@ def main():
                                "ramp chi_max=0.2" % (head, spec.nx, spec.ny, args.storage.upper()),
                    "nx": spec.nx, "ny": spec.ny, "variant": head, "storage": args.storage,
                    "diagnostics_every": 100},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS,
-                     "traffic": counter_traffic(r["tuning"]) if args.storage == "f32"
-                     and args.n == 4096 and head == "II" else None,
-                     "algorithmic_bytes_per_launch": bytes_per_cell * cells,
-                     "steps_per_launch": r["steps_per_launch"],
-                     "kernel_ms": r["kernel_ms"],
-                     "single_step_equivalent_gbps": bytes_per_cell * r["mlups"] / 1e3},
+        "roofline": roofline,
         "per_variant": {v: {"mlups": x["mlups"], "kernel_ms": x["kernel_ms"],
                             "steps_per_launch": x["steps_per_launch"],
                             "achieved_gbps": bytes_per_cell * cells / (x["kernel_ms"] * 1e-3) / 1e9,
@@ -414,7 +436,7 @@ def main():
         "copy_kernel_gbps": copy_gbps,
     }
     if copy_gbps:
-        out["roofline"]["frac_of_copy"] = achieved / copy_gbps
+        out["roofline"]["hbm_frac_of_copy"] = hbm_gbps / copy_gbps
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)

@@ -8,12 +8,14 @@ import os
 import shutil
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip", "lbm_batch.hip"]
+SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip", "lbm_batch.hip",
+           "lbm_strip_f64.hip", "lbm_strip_f32.hip", "lbm_strip_f16.hip"]
 
 # - no automatic FMA contraction: the kernels place their fused multiply-adds
 #   explicitly, so every launch shape gives the same bits;
@@ -33,20 +35,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     cc = hipcc()
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, src.rsplit(".", 1)[0] + ".o")
-        lang = ["-x", "hip"]
-        cmd = [cc] + lang + [f for f in FLAGS if f != "-shared"] + [
-            "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([cc, "-x", "hip"] + [f for f in FLAGS if f != "-shared"] + [
+            "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    # the translation units are independent: compile them side by side
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+        while len([p for p in procs if p.poll() is None]) >= jobs:
+            time.sleep(0.2)
+        procs.append(subprocess.Popen(cmd))
+    failed = [c for c, p in zip(cmds, procs) if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

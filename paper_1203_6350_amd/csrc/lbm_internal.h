@@ -35,6 +35,13 @@ enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MA
 // k = 2..4 time steps in one launch (src at t -> dst at t + k).
 hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void *dst,
                               hipStream_t stream);
+// per storage type (lbm_strip_f64/f32/f16.hip)
+hipError_t launch_multi_f64(const StepConfig &c, int k, const void *src, void *dst,
+                            hipStream_t stream);
+hipError_t launch_multi_f32(const StepConfig &c, int k, const void *src, void *dst,
+                            hipStream_t stream);
+hipError_t launch_multi_f16(const StepConfig &c, int k, const void *src, void *dst,
+                            hipStream_t stream);
 bool vec_supported(const StepConfig &c);
 // FP16 mode: stored value = deviation / storage_scale (a power of two).
 double storage_scale(const StepConfig &c, int i);

@@ -10,11 +10,11 @@
 // coalesced and the reads of the six x-shifted planes are offset by one
 // element.
 #include <cmath>
-#include <atomic>
 #include <type_traits>
 
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include "lbm_launch.h"
 
 namespace lbm {
 
@@ -25,45 +25,6 @@ namespace lbm {
 double storage_scale(const StepConfig &c, int i) {
   if (c.storage != 2) return 1.0;
   return std::exp2(std::nearbyint(std::log2(w_of(i) * c.f16_scale)));
-}
-
-template <typename S>
-struct Lat {
-  typedef typename Store<S>::C C;
-  int nx, ny;
-  int64_t pitch, ps;
-  C scale[9], inv_scale[9];
-};
-
-template <typename S>
-static Lat<S> make_lat(const StepConfig &c) {
-  typedef typename Store<S>::C C;
-  Lat<S> L;
-  L.nx = c.nx;
-  L.ny = c.ny;
-  L.pitch = c.pitch;
-  L.ps = c.plane_stride;
-  for (int i = 0; i < 9; ++i) {
-    const double sc = storage_scale(c, i);
-    L.scale[i] = C(sc);
-    L.inv_scale[i] = C(1.0 / sc);
-  }
-  return L;
-}
-
-template <typename C>
-static CollideParams<C> make_params(const StepConfig &c) {
-  CollideParams<C> p;
-  for (int k = 0; k < 9; ++k) p.s[k] = C(c.s[k]);
-  p.n = C(c.n);
-  p.m = C(c.m);
-  p.rho_b = C(c.rho_b);
-  p.ubx = C(c.ubx);
-  p.uby = C(c.uby);
-  p.dcf0 = C(c.dcf[0]);
-  p.dcf1 = C(c.dcf[1]);
-  p.dcf2 = C(c.dcf[2]);
-  return p;
 }
 
 __device__ __forceinline__ int wrapi(int a, int n) {
@@ -205,429 +166,6 @@ __global__ __launch_bounds__(BX) void step_vec(
   for (int i = 0; i < 9; ++i) store16<NT>(dst + i * ps + r0 + x0, out[i]);
 }
 
-// ---------------------------------------------------------------- several steps per launch
-// Temporal blocking: one launch advances the lattice by K = 2, 3 or 4 time
-// steps, reading and writing it once.
-//
-// Each wave owns a strip of STRIP = 64 - 2K output columns of one chunk of
-// rows: lane l holds column X0 - K + l (mod nx), so the 64 lanes cover the
-// strip plus K halo columns on each side. The wave marches down the rows.
-// When row a of the input lattice arrives, the lanes compute step 1 at row
-// a - 1, step 2 at row a - 2, ..., step K at row a - K, each from the rows
-// the step before produced. Pulls along x come from the neighbouring lanes
-// (DPP wave shifts); pulls along y from registers carried over rows. A row's
-// populations are consumed in three groups, each by one step at one row:
-// {4, 7, 8} (c_y = -1) at the row above, {0, 1, 3} (c_y = 0) at the row
-// itself, {2, 5, 6} (c_y = +1) at the row below. After step j a lane's result
-// is valid on lanes j..63-j; step K's lanes K..63-K are the strip's outputs.
-//
-// Every intermediate result is rounded through the storage format before
-// the next step reads it, exactly as a stored and reloaded value would be,
-// so the result is bit-identical to K launches of the one-step kernels.
-//
-// Everything that indexes rows is uniform across the wave (scalar
-// registers); per lane only the column offset differs. The row loop is
-// unrolled over six phases (the row position mod 6) so that each carried
-// group keeps a fixed register per phase, which leaves no register moves.
-//
-// A workgroup of nw waves takes nw adjacent strips of one chunk (a strip
-// group) and its waves pass a barrier at every row, so their row accesses
-// reach memory together as one contiguous run of nw * STRIP elements per
-// plane. Strips past the right edge repeat the last strip and store nothing,
-// so every wave of a workgroup runs the same number of rows and barriers.
-
-template <int K>
-constexpr int strip_width() {
-  return 64 - 2 * K;
-}
-template <int M>
-__device__ constexpr int md(int x) {  // x mod M in [0, M)
-  return ((x % M) + M) % M;
-}
-
-template <typename S>
-__device__ __forceinline__ typename Store<S>::C roundtrip(typename Store<S>::C v,
-                                                          typename Store<S>::C scale,
-                                                          typename Store<S>::C inv_scale) {
-  S t;
-  Store<S>::store(&t, v, inv_scale);
-  return Store<S>::load(&t, scale);
-}
-
-// DPP wave shifts: wave_shr:1 gives lane l the value of lane l - 1,
-// wave_shl:1 the value of lane l + 1 (lanes 0 and 63 receive 0; their
-// results are never stored).
-__device__ __forceinline__ int wave_shr1(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
-}
-__device__ __forceinline__ int wave_shl1(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
-}
-__device__ __forceinline__ float lane_up(float v) {  // value of lane - 1
-  return __builtin_bit_cast(float, wave_shr1(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ float lane_down(float v) {  // value of lane + 1
-  return __builtin_bit_cast(float, wave_shl1(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double lane_up(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const unsigned lo = (unsigned)wave_shr1((int)b), hi = (unsigned)wave_shr1((int)(b >> 32));
-  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ __forceinline__ double lane_down(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const unsigned lo = (unsigned)wave_shl1((int)b), hi = (unsigned)wave_shl1((int)(b >> 32));
-  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Pull at one row: rm = the row above's {2, 5, 6}, r0 = this row's
-// {0, 1, 3}, rp = the row below (all nine, only 4, 7, 8 read).
-template <typename C>
-__device__ __forceinline__ void pull(const C rm[3], const C r0[3], C rp4, C rp7, C rp8,
-                                     C g[9]) {
-  g[0] = r0[0];
-  g[1] = lane_up(r0[1]);
-  g[3] = lane_down(r0[2]);
-  g[2] = rm[0];
-  g[5] = lane_up(rm[1]);
-  g[6] = lane_down(rm[2]);
-  g[4] = rp4;
-  g[7] = lane_down(rp7);
-  g[8] = lane_up(rp8);
-}
-
-// Carried state of one wave. Ring slots are indexed by the row's position
-// q = row - (Y0 - K) within the chunk (q >= 0): a group live over two
-// iterations sits in slot q % 2, one live over three in slot q % 3.
-template <typename C, int K>
-struct StripState {
-  C a478[3][3];         // input rows: populations 4, 7, 8 (loaded two rows ahead)
-  C a013[3][3];         // input rows: populations 0, 1, 3
-  C a256[3][3];         // input rows: populations 2, 5, 6
-  C craw[6];            // sponge input (chi_raw) of the rows, slot q % 6
-  C b013[K - 1][2][3];  // results of steps 1..K-1: populations 0, 1, 3
-  C b256[K - 1][3][3];  // results of steps 1..K-1: populations 2, 5, 6
-};
-
-template <typename S, int VAR, int CHI, int K>
-struct StripCtx {
-  typedef typename Store<S>::C C;
-  const S *src;
-  S *dst;
-  int64_t ps, pitch;
-  unsigned col;        // this lane's column
-  unsigned col_bytes;  // col * sizeof(S)
-  unsigned out_bytes;  // (lane - K) * sizeof(S): output offset from the strip start
-  bool store_lane;
-  int nw;              // waves per workgroup
-  int nx, ny, Y0, X0;
-  C cx_chi;
-  const C *chi_field, *chiy;
-  C scale[9], inv_scale[9];
-  CollideParams<C> p;
-  C mref[9];
-
-  __device__ __forceinline__ int wrap_row(int r) const {
-    r %= ny;
-    return r < 0 ? r + ny : r;
-  }
-  // global-memory views: elements move as same-size integers (the FP16
-  // element type is a class, which address-space pointers do not copy)
-  typedef typename std::conditional<
-      sizeof(S) == 2, uint16_t,
-      typename std::conditional<sizeof(S) == 4, uint32_t, uint64_t>::type>::type Bits;
-  typedef __attribute__((address_space(1))) Bits GS;
-  typedef __attribute__((address_space(1))) char GChar;
-  // The row's address is uniform across the wave; routing it through
-  // readfirstlane keeps it in scalar registers, so the load adds only the
-  // lane's 32-bit byte offset to it (no per-lane 64-bit addresses).
-  static __device__ __forceinline__ GChar *uniform_ptr(const void *p) {
-    const uint64_t u = (uint64_t)p;
-    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
-    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
-    return (GChar *)(lo | (hi << 32));
-  }
-  // The lane's byte offset is re-materialised at each use (an empty asm
-  // that emits nothing), so the 32-bit offset reaches the load itself and
-  // the instruction takes the scalar base + 32-bit vector offset form.
-  static __device__ __forceinline__ unsigned local(unsigned v) {
-    asm volatile("" : "+v"(v));
-    return v;
-  }
-  __device__ __forceinline__ C ld(int i, int r) const {
-    const GS *q =
-        (const GS *)(uniform_ptr(src + i * ps + (int64_t)r * pitch) + local(col_bytes));
-    const Bits b = *q;
-    S v;
-    __builtin_memcpy(&v, &b, sizeof(S));
-    return Store<S>::load(&v, scale[i]);
-  }
-  // store of population i at this lane's output column of row y
-  __device__ __forceinline__ void st_out(int i, int y, C v) const {
-    GS *q = (GS *)(uniform_ptr(dst + i * ps + (int64_t)y * pitch + X0) + local(out_bytes));
-    S t;
-    Store<S>::store(&t, v, inv_scale[i]);
-    Bits b;
-    __builtin_memcpy(&b, &t, sizeof(S));
-    *q = b;
-  }
-  // Sponge input of row r: the field value at this lane, or chi_y[r] of a
-  // separable profile (combined with chi_x by chi_of when used).
-  __device__ __forceinline__ C chi_raw(int r) const {
-    if (CHI == CHI_ZERO) return C(0);
-    if (CHI == CHI_FIELD) return chi_field[(int64_t)r * pitch + col];
-    return chiy[r];
-  }
-  __device__ __forceinline__ C chi_of(C raw) const {
-    if (CHI == CHI_SEP_MAX) return cx_chi > raw ? cx_chi : raw;
-    if (CHI == CHI_SEP_SUM) return cx_chi + raw;
-    return raw;
-  }
-  // Loads of input row r (position Q).
-  template <int Q>
-  __device__ __forceinline__ void load_478(StripState<C, K> &st, int r) const {
-    st.a478[md<3>(Q)][0] = ld(4, r);
-    st.a478[md<3>(Q)][1] = ld(7, r);
-    st.a478[md<3>(Q)][2] = ld(8, r);
-  }
-  template <int Q>
-  __device__ __forceinline__ void load_013(StripState<C, K> &st, int r) const {
-    st.a013[md<3>(Q)][0] = ld(0, r);
-    st.a013[md<3>(Q)][1] = ld(1, r);
-    st.a013[md<3>(Q)][2] = ld(3, r);
-  }
-  template <int Q>
-  __device__ __forceinline__ void load_256(StripState<C, K> &st, int r) const {
-    st.a256[md<3>(Q)][0] = ld(2, r);
-    st.a256[md<3>(Q)][1] = ld(5, r);
-    st.a256[md<3>(Q)][2] = ld(6, r);
-  }
-  // Keep the result of step JJ at row position Q for the rows below.
-  template <int JJ, int Q>
-  __device__ __forceinline__ void keep(StripState<C, K> &st, const C g[9]) const {
-    st.b013[JJ - 1][md<2>(Q)][0] = g[0];
-    st.b013[JJ - 1][md<2>(Q)][1] = g[1];
-    st.b013[JJ - 1][md<2>(Q)][2] = g[3];
-    st.b256[JJ - 1][md<3>(Q)][0] = g[2];
-    st.b256[JJ - 1][md<3>(Q)][1] = g[5];
-    st.b256[JJ - 1][md<3>(Q)][2] = g[6];
-  }
-
-  // Iteration at input row a (position P, taken mod 6): load what later
-  // steps read of rows a + 1 (periodic row index r_next) and a + 2 (r_next2,
-  // populations 4, 7, 8, which step 1 needs soonest), then steps 1..J at rows
-  // a - 1 .. a - J. left = iterations remaining including this one.
-  template <int P, int J>
-  __device__ __forceinline__ void iter(StripState<C, K> &st, int a, int r_next, int r_next2,
-                                       int left) const {
-    if (nw > 1) __builtin_amdgcn_s_barrier();  // rows of the strip group in step
-    if (left > 2) load_478<P + 2>(st, r_next2);
-    if (left > 2) load_013<P + 1>(st, r_next);
-    // step 1 at row a - 1 from input rows a - 2, a - 1, a
-    C g[9];
-    {
-      const C *rp = st.a478[md<3>(P)];
-      pull<C>(st.a256[md<3>(P - 2)], st.a013[md<3>(P - 1)], rp[0], rp[1], rp[2], g);
-    }
-    // row a - 2's {2, 5, 6} are consumed: its slot takes row a + 1's
-    if (left > 3) load_256<P + 1>(st, r_next);
-    const C chi1 = chi_of(st.craw[md<6>(P - 1)]);
-    // the sponge input of row a + 1 is read after this use, so waiting for
-    // it does not hold up this row
-    if (left > 2) st.craw[md<6>(P + 1)] = chi_raw(r_next);
-    collide<C, VAR>(g, chi1, p, mref);
-    chain<P, J, 2>(st, g, a);
-  }
-
-  // g = result of step j - 1 at row a - (j - 1); run steps j..J.
-  template <int P, int J, int j>
-  __device__ __forceinline__ void chain(StripState<C, K> &st, C g[9], int a) const {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = roundtrip<S>(g[i], scale[i], inv_scale[i]);
-    if constexpr (j > J) {
-      keep<j - 1, P - (j - 1)>(st, g);
-    } else {
-      // step j at row a - j from step j - 1 rows a - j - 1, a - j, a - j + 1
-      C o[9];
-      pull<C>(st.b256[j - 2][md<3>(P - j - 1)], st.b013[j - 2][md<2>(P - j)], g[4], g[7], g[8],
-              o);
-      keep<j - 1, P - (j - 1)>(st, g);
-      collide<C, VAR>(o, chi_of(st.craw[md<6>(P - j)]), p, mref);
-      if constexpr (j == K) {
-        if (store_lane) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) st_out(i, a - K, o[i]);
-        }
-      } else {
-        chain<P, J, j + 1>(st, o, a);
-      }
-    }
-  }
-};
-
-template <typename S, int VAR, int CHI, int K>
-__global__ __launch_bounds__(512) void step_multi_strip(
-    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
-    CollideParams<typename Store<S>::C> p,
-    const typename Store<S>::C *__restrict__ chi_field,
-    const typename Store<S>::C *__restrict__ chix,
-    const typename Store<S>::C *__restrict__ chiy, int rows_per_chunk,
-    int nstrips, int ngroups, int wg_per_xcd, int nwg) {
-  typedef typename Store<S>::C C;
-  constexpr int W = strip_width<K>();
-  // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
-  // contiguous range of work (a band of chunk rows) so neighbouring strips
-  // and chunks share an L2
-  const int v = (blockIdx.x & 7) * wg_per_xcd + (blockIdx.x >> 3);
-  if (v >= nwg) return;
-  const int lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
-  const int chunk = v / ngroups, group = v - chunk * ngroups;
-  int strip = group * nw + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const bool idle = strip >= nstrips;
-  if (idle) strip = nstrips - 1;
-  StripCtx<S, VAR, CHI, K> c;
-  c.src = src;
-  c.dst = dst;
-  c.ps = L.ps;
-  c.pitch = L.pitch;
-  c.nx = L.nx;
-  c.ny = L.ny;
-  c.nw = nw;
-  c.X0 = strip * W;
-  c.Y0 = chunk * rows_per_chunk;
-  const int R = min(rows_per_chunk, L.ny - c.Y0);  // output rows of the chunk
-  int col = (c.X0 - K + lane) % L.nx;
-  if (col < 0) col += L.nx;
-  c.col = (unsigned)col;
-  c.col_bytes = (unsigned)col * (unsigned)sizeof(S);
-  c.out_bytes = (unsigned)(lane - K) * (unsigned)sizeof(S);
-  c.store_lane = !idle && lane >= K && lane < K + W && c.X0 + lane - K < L.nx;
-  c.cx_chi = (CHI == CHI_SEP_MAX || CHI == CHI_SEP_SUM) ? chix[col] : C(0);
-  c.chi_field = chi_field;
-  c.chiy = chiy;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    c.scale[i] = L.scale[i];
-    c.inv_scale[i] = L.inv_scale[i];
-  }
-  c.p = p;
-  if (VAR == V_I || VAR == V_II) ref_moments(p, c.mref);
-
-  StripState<C, K> st;
-  // Positions q = 0, 1, 2, 3 (rows Y0 - K .. Y0 - K + 3): step 1 starts at
-  // q = 1, so row q = 0 supplies only {2, 5, 6}; {4, 7, 8} run two rows ahead.
-  auto next = [&](int rr) { return rr + 1 == L.ny ? 0 : rr + 1; };
-  int r = c.wrap_row(c.Y0 - K);
-  c.template load_256<0>(st, r);
-  r = next(r);
-  c.template load_256<1>(st, r);
-  c.template load_013<1>(st, r);
-  st.craw[1] = c.chi_raw(r);
-  r = next(r);
-  c.template load_478<2>(st, r);
-  c.template load_013<2>(st, r);
-  c.template load_256<2>(st, r);
-  st.craw[2] = c.chi_raw(r);
-  c.template load_478<3>(st, next(r));
-  // Iterations q = 2 .. R + 2K - 1 at input rows a = Y0 - K + q. Step j runs
-  // from q = 2j on: q = 2, 3 run step 1, q = 4, 5 steps 1-2, q = 6, 7 steps
-  // 1-3, and from q = 2K on all K steps run (R iterations).
-  int a = c.Y0 - K + 2;
-  int left = R + 2 * K - 2;
-  r = next(r);
-  c.template iter<2, 1>(st, a, r, next(r), left--);
-  ++a;
-  r = next(r);
-  c.template iter<3, 1>(st, a, r, next(r), left--);
-  if constexpr (K >= 3) {
-    ++a;
-    r = next(r);
-    c.template iter<4, 2>(st, a, r, next(r), left--);
-    ++a;
-    r = next(r);
-    c.template iter<5, 2>(st, a, r, next(r), left--);
-  }
-  if constexpr (K >= 4) {
-    ++a;
-    r = next(r);
-    c.template iter<0, 3>(st, a, r, next(r), left--);
-    ++a;
-    r = next(r);
-    c.template iter<1, 3>(st, a, r, next(r), left--);
-  }
-#define LBM_STRIP_ITER(PH)                                          \
-  ++a;                                                              \
-  r = next(r);                                                      \
-  c.template iter<(2 * K + PH) % 6, K>(st, a, r, next(r), left);    \
-  if (--left == 0) break;
-  for (;;) {
-    LBM_STRIP_ITER(0)
-    LBM_STRIP_ITER(1)
-    LBM_STRIP_ITER(2)
-    LBM_STRIP_ITER(3)
-    LBM_STRIP_ITER(4)
-    LBM_STRIP_ITER(5)
-  }
-#undef LBM_STRIP_ITER
-}
-
-// Workgroups of the multi-step kernel that fit on the device at once, for
-// workgroups of nw waves (nw = 1, 2, 4 or 8).
-template <typename S, int VAR, int CHI, int K>
-static int64_t multi_step_capacity(int nw) {
-  static std::atomic<int64_t> cache[4] = {{-1}, {-1}, {-1}, {-1}};
-  const int slot = nw == 1 ? 0 : (nw == 2 ? 1 : (nw == 4 ? 2 : 3));
-  int64_t cap = cache[slot].load(std::memory_order_relaxed);
-  if (cap >= 0) return cap;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_multi_strip<S, VAR, CHI, K>,
-                                                   64 * nw, 0) != hipSuccess)
-    return 0;
-  cap = (int64_t)cus * per_cu;
-  cache[slot].store(cap, std::memory_order_relaxed);
-  return cap;
-}
-
-template <typename S, int VAR, int CHI, int K>
-static hipError_t launch_multi_t(const StepConfig &c, const void *src, void *dst,
-                                 hipStream_t stream) {
-  typedef typename Store<S>::C C;
-  Lat<S> L = make_lat<S>(c);
-  CollideParams<C> p = make_params<C>(c);
-  const int nw = c.block == 64 ? 1 : (c.block == 128 ? 2 : (c.block == 256 ? 4 : 8));
-  const int nstrips = (c.nx + strip_width<K>() - 1) / strip_width<K>();
-  const int ngroups = (nstrips + nw - 1) / nw;
-  int rows = c.rows;
-  if (rows <= 0) {
-    // chunk height that lets every workgroup be resident at once
-    const int64_t cap = multi_step_capacity<S, VAR, CHI, K>(nw);
-    const int64_t chunks = cap > ngroups ? cap / ngroups : 1;
-    rows = (int)((c.ny + chunks - 1) / chunks);
-  }
-  const int nchunks = (c.ny + rows - 1) / rows;
-  const int64_t nwg = (int64_t)ngroups * nchunks;
-  const int64_t per_xcd = (nwg + 7) / 8;
-  if (8 * per_xcd > 0x7fffffff) return hipErrorInvalidValue;
-  step_multi_strip<S, VAR, CHI, K><<<dim3((unsigned)(8 * per_xcd)), dim3(64 * nw), 0, stream>>>(
-      (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
-      (const C *)c.chi_y, rows, nstrips, ngroups, (int)per_xcd, (int)nwg);
-  return hipGetLastError();
-}
-
-template <typename S, int VAR, int CHI>
-static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void *dst,
-                               hipStream_t stream) {
-  switch (k) {
-    case 2: return launch_multi_t<S, VAR, CHI, 2>(c, src, dst, stream);
-    case 3: return launch_multi_t<S, VAR, CHI, 3>(c, src, dst, stream);
-    case 4: return launch_multi_t<S, VAR, CHI, 4>(c, src, dst, stream);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename S, int VAR, int CHI, int BX>
 static hipError_t launch_generic(const StepConfig &c, const void *src, void *dst,
                                  hipStream_t stream) {
@@ -690,20 +228,9 @@ static hipError_t launch_step_t(const StepConfig &c, const void *src,
   }
 }
 
-// k = 1: one step (one-cell or vector kernel); k = 2..4: k steps in one
-// launch of the strip kernel.
 template <typename S, int VAR>
 static hipError_t dispatch_chi(const StepConfig &c, const void *src, void *dst,
-                               hipStream_t s, int k) {
-  if (k > 1) {
-    switch (c.chi_mode) {
-      case CHI_ZERO: return launch_multi<S, VAR, CHI_ZERO>(c, k, src, dst, s);
-      case CHI_FIELD: return launch_multi<S, VAR, CHI_FIELD>(c, k, src, dst, s);
-      case CHI_SEP_MAX: return launch_multi<S, VAR, CHI_SEP_MAX>(c, k, src, dst, s);
-      case CHI_SEP_SUM: return launch_multi<S, VAR, CHI_SEP_SUM>(c, k, src, dst, s);
-    }
-    return hipErrorInvalidValue;
-  }
+                               hipStream_t s) {
   switch (c.chi_mode) {
     case CHI_ZERO: return launch_step_t<S, VAR, CHI_ZERO>(c, src, dst, s);
     case CHI_FIELD: return launch_step_t<S, VAR, CHI_FIELD>(c, src, dst, s);
@@ -715,13 +242,13 @@ static hipError_t dispatch_chi(const StepConfig &c, const void *src, void *dst,
 
 template <typename S>
 static hipError_t dispatch_var(const StepConfig &c, const void *src, void *dst,
-                               hipStream_t s, int k) {
+                               hipStream_t s) {
   switch (c.variant) {
-    case V_NONE: return dispatch_chi<S, V_NONE>(c, src, dst, s, k);
-    case V_I: return dispatch_chi<S, V_I>(c, src, dst, s, k);
-    case V_II: return dispatch_chi<S, V_II>(c, src, dst, s, k);
-    case V_III: return dispatch_chi<S, V_III>(c, src, dst, s, k);
-    case V_VISC: return dispatch_chi<S, V_VISC>(c, src, dst, s, k);
+    case V_NONE: return dispatch_chi<S, V_NONE>(c, src, dst, s);
+    case V_I: return dispatch_chi<S, V_I>(c, src, dst, s);
+    case V_II: return dispatch_chi<S, V_II>(c, src, dst, s);
+    case V_III: return dispatch_chi<S, V_III>(c, src, dst, s);
+    case V_VISC: return dispatch_chi<S, V_VISC>(c, src, dst, s);
   }
   return hipErrorInvalidValue;
 }
@@ -729,9 +256,9 @@ static hipError_t dispatch_var(const StepConfig &c, const void *src, void *dst,
 hipError_t launch_step(const StepConfig &c, const void *src, void *dst,
                        hipStream_t stream) {
   switch (c.storage) {
-    case 0: return dispatch_var<double>(c, src, dst, stream, 1);
-    case 1: return dispatch_var<float>(c, src, dst, stream, 1);
-    case 2: return dispatch_var<__half>(c, src, dst, stream, 1);
+    case 0: return dispatch_var<double>(c, src, dst, stream);
+    case 1: return dispatch_var<float>(c, src, dst, stream);
+    case 2: return dispatch_var<__half>(c, src, dst, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -740,9 +267,9 @@ hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void 
                               hipStream_t stream) {
   if (k < 2 || k > 4) return hipErrorInvalidValue;
   switch (c.storage) {
-    case 0: return dispatch_var<double>(c, src, dst, stream, k);
-    case 1: return dispatch_var<float>(c, src, dst, stream, k);
-    case 2: return dispatch_var<__half>(c, src, dst, stream, k);
+    case 0: return launch_multi_f64(c, k, src, dst, stream);
+    case 1: return launch_multi_f32(c, k, src, dst, stream);
+    case 2: return launch_multi_f16(c, k, src, dst, stream);
   }
   return hipErrorInvalidValue;
 }
