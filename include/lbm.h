@@ -227,9 +227,13 @@ const char *lbm_last_error(void);
 /* ---- batched stepping of many lattices --------------------------------
  * A batch steps many independent lattices (each an lbm_handle with its own
  * size, relaxation rates, damping variant, sponge and reference state) with
- * one persistent launch per time step, captured in HIP graphs. All members
- * must share the storage mode and the device. Each member's result is
- * bit-identical to stepping it alone with lbm_step.
+ * persistent launches captured in HIP graphs: by default each launch
+ * advances every member by K steps (the strip kernel over a table of work
+ * items; K = 4 for FP32 storage, 3 for FP64 and FP16) and a member's
+ * remainder of fewer than K steps in a tick runs as one-step launches over
+ * a table of 256-cell tiles. All members must share the storage mode and the
+ * device. Each member's result is bit-identical to stepping it alone with
+ * lbm_step.
  * While a batch has work in flight its members must not be used on their
  * own; lbm_batch_sync makes them usable again. Member parameters (sponge,
  * q_ref, tuning) are read at every tick, so they may change between ticks.
@@ -255,8 +259,19 @@ int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps);
 int lbm_batch_set_members(lbm_batch *b, lbm_handle *const *members,
                           int32_t count);
 
-/* Persistent workgroups per compute unit (1..64, default 8). */
+/* Persistent workgroups per compute unit of the one-step tile kernel
+ * (1..64, default 8). */
 int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu);
+
+/* Launch shape of the batch (see lbm_tuning): kernel 0 or 1 = one-step
+ * launches over 256-cell tiles only (block and rows ignored); kernel 2, 3
+ * or 4 = that many steps per launch of the strip kernel, `block` threads per
+ * workgroup (64, 128, 256 or 512: adjacent strips of one member), `rows`
+ * rows per work item (1..4096, or 0 for a height at which the items about
+ * fill the device once). Rebuilds the work-item table; synchronises the
+ * batch stream. Results are bit-identical for every shape. */
+int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t);
+int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t);
 
 int lbm_batch_sync(lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);

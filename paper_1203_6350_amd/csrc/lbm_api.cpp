@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -641,7 +642,18 @@ struct lbm_batch {
   size_t dom_cap = 0, tile_cap = 0;
   int cus = 1;
   int blocks_per_cu = 8;
-  std::map<int, hipGraphExec_t> graphs;  // keyed by (tick, grid)
+  // K-step strip launches (multi_k = 0: one-step tile launches only)
+  int multi_k = 0;
+  int multi_nw = 1;    // waves per workgroup
+  int multi_rows = 0;  // rows per work item, 0: fit the device
+  int multi_grid = 0;  // persistent workgroups of the strip kernel
+  int4 *d_items = nullptr;
+  int *d_nitems = nullptr;
+  int nitems = 0;
+  size_t item_cap = 0;
+  // graphs keyed by (K or 0, K-step launches or ticks, remainder launches,
+  // tile workgroups per CU, strip workgroup waves)
+  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -679,10 +691,13 @@ void free_graphs(lbm_batch *b) {
   b->graphs.clear();
 }
 
-// Instantiated graph of `tick` batched launches (k = 0 .. tick-1).
-int batch_graph(lbm_batch *b, int tick, hipGraphExec_t *out) {
+// Instantiated graph of one tick: `nmulti` K-step strip launches
+// (j = 0 .. nmulti-1) then `nsingle` one-step tile launches (k = 0 ..
+// nsingle-1; with K-step launches these take the members' remainders).
+int batch_graph(lbm_batch *b, int nmulti, int nsingle, hipGraphExec_t *out) {
   const int grid = b->cus * b->blocks_per_cu;
-  const int key = tick * 4096 + b->blocks_per_cu;
+  const auto key = std::make_tuple(b->multi_k, nmulti, nsingle, b->blocks_per_cu,
+                                   b->multi_k ? b->multi_nw : 0);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -690,8 +705,12 @@ int batch_graph(lbm_batch *b, int tick, hipGraphExec_t *out) {
   }
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   hipError_t e = hipSuccess;
-  for (int k = 0; k < tick && e == hipSuccess; ++k)
-    e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, b->stream);
+  for (int j = 0; j < nmulti && e == hipSuccess; ++j)
+    e = lbm::launch_batch_multi(b->storage, b->multi_k, b->multi_nw, b->d_doms, b->d_items,
+                                b->d_nitems, b->multi_grid, j, b->stream);
+  for (int k = 0; k < nsingle && e == hipSuccess; ++k)
+    e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, b->multi_k,
+                          b->stream);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -718,6 +737,8 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->d_doms) (void)hipFree(b->d_doms);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_ntiles) (void)hipFree(b->d_ntiles);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_nitems) (void)hipFree(b->d_nitems);
   for (int k = 0; k < 2; ++k) {
     if (b->h_doms[k]) (void)hipHostFree(b->h_doms[k]);
     if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
@@ -741,6 +762,49 @@ int validate_members(lbm_handle *const *members, int32_t count) {
     for (int32_t j = 0; j < i; ++j)
       if (members[j] == members[i]) return fail(LBM_EINVAL, "members must be distinct");
   }
+  return LBM_OK;
+}
+
+// Rebuild the strip work-item table for the batch's members and K-step
+// shape; reuses the device buffer (and so the captured graphs) when it fits.
+// The stream must be idle.
+int build_items(lbm_batch *b) {
+  if (!b->multi_k) return LBM_OK;
+  const int W = 64 - 2 * b->multi_k;
+  const int nw = b->multi_nw;
+  const int per_cu = lbm::batch_multi_per_cu(b->storage, b->multi_k, nw);
+  if (per_cu < 1) return fail(LBM_EDEVICE, "the strip kernel does not fit on a compute unit");
+  b->multi_grid = b->cus * per_cu;
+  int64_t group_rows = 0;
+  for (lbm_handle *h : b->members) {
+    const int64_t ngroups = ((h->user.nx + W - 1) / W + nw - 1) / nw;
+    group_rows += ngroups * h->user.ny;
+  }
+  const int64_t rows = b->multi_rows > 0 ? b->multi_rows
+                                         : std::max<int64_t>(1, (group_rows + b->multi_grid - 1) /
+                                                                    b->multi_grid);
+  std::vector<int4> items;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const lbm_handle *h = b->members[i];
+    const int nstrips = (h->user.nx + W - 1) / W;
+    for (int64_t y0 = 0; y0 < h->user.ny; y0 += rows)
+      for (int s0 = 0; s0 < nstrips; s0 += nw)
+        items.push_back(make_int4((int)i, s0, (int)y0, (int)std::min<int64_t>(rows, h->user.ny - y0)));
+  }
+  if (items.size() > (size_t)0x7fffffff) return fail(LBM_EINVAL, "too many work items");
+  if (items.size() > b->item_cap) {
+    free_graphs(b);
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    b->item_cap = 0;
+    const size_t cap = std::max<size_t>(items.size(), (size_t)(1.5 * items.size()));
+    HIP_TRY(hipMalloc((void **)&b->d_items, sizeof(int4) * cap), "batch work items");
+    b->item_cap = cap;
+  }
+  b->nitems = (int)items.size();
+  HIP_TRY(hipMemcpy(b->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice),
+          "hipMemcpy(items)");
+  HIP_TRY(hipMemcpy(b->d_nitems, &b->nitems, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy(nitems)");
   return LBM_OK;
 }
 
@@ -786,7 +850,7 @@ int batch_set_members_impl(lbm_batch *b, lbm_handle *const *members, int32_t cou
   HIP_TRY(hipMemcpy(b->d_ntiles, &b->ntiles, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy(ntiles)");
   b->members.assign(members, members + count);
   b->storage = members[0]->user.storage;
-  return LBM_OK;
+  return build_items(b);
 }
 
 }  // namespace
@@ -812,6 +876,10 @@ int lbm_batch_create(lbm_handle *const *members, int32_t count, void *stream,
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_ntiles, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_nitems, sizeof(int));
+  // default shape: K-step strip launches (K = 4 for FP32, 3 for FP64 and FP16)
+  b->storage = members[0]->user.storage;
+  b->multi_k = b->storage == LBM_STORAGE_F32 ? 4 : 3;
   for (int k = 0; k < 2 && e == hipSuccess; ++k)
     e = hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -839,6 +907,33 @@ int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu) {
   return LBM_OK;
 }
 
+int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t) {
+  if (!b || !t) return fail(LBM_EINVAL, "NULL argument");
+  if (t->kernel < 0 || t->kernel > lbm::KERNEL_MULTI_MAX)
+    return fail(LBM_EINVAL, "kernel must be 0, 1, 2, 3 or 4");
+  if (t->kernel >= 2) {
+    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
+      return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512");
+    if (t->rows < 0 || t->rows > 4096) return fail(LBM_EINVAL, "rows must be 0 or 1..4096");
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  b->multi_k = t->kernel >= 2 ? t->kernel : 0;
+  if (b->multi_k) {
+    b->multi_nw = t->block / 64;
+    b->multi_rows = t->rows;
+  }
+  return build_items(b);
+}
+
+int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t) {
+  if (!b || !t) return fail(LBM_EINVAL, "NULL argument");
+  t->kernel = b->multi_k;
+  t->block = b->multi_k ? 64 * b->multi_nw : lbm::BATCH_TILE;
+  t->nontemporal = 0;
+  t->rows = b->multi_k ? b->multi_rows : 0;
+  return LBM_OK;
+}
+
 int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   if (tick < 1 || tick > 4096) return fail(LBM_EINVAL, "tick must be 1..4096");
@@ -860,13 +955,26 @@ int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
   HIP_TRY(hipMemcpyAsync(b->d_doms, hd, sizeof(lbm::BatchDomain) * n,
                          hipMemcpyHostToDevice, b->stream), "hipMemcpy(descriptors)");
   HIP_TRY(hipEventRecord(b->copied[sl], b->stream), "hipEventRecord");
+  // with K-step launches, member i takes st / K of them and then st mod K
+  // one-step launches; every launch flips its current lattice once
+  const int K = b->multi_k;
+  int nmulti = 0, nsingle = tick;
+  if (K) {
+    nsingle = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const int st = member_steps ? member_steps[i] : tick;
+      nmulti = std::max(nmulti, st / K);
+      nsingle = std::max(nsingle, st % K);
+    }
+  }
   hipGraphExec_t ex = nullptr;
-  int rc = batch_graph(b, tick, &ex);
+  int rc = batch_graph(b, nmulti, nsingle, &ex);
   if (rc) return rc;
   HIP_TRY(hipGraphLaunch(ex, b->stream), "hipGraphLaunch");
   for (size_t i = 0; i < n; ++i) {
     const int st = member_steps ? member_steps[i] : tick;
-    b->members[i]->cur ^= st & 1;
+    const int launches = K ? st / K + st % K : st;
+    b->members[i]->cur ^= launches & 1;
     b->members[i]->steps += st;
   }
   return LBM_OK;

@@ -12,7 +12,10 @@
 // graph of launches stays valid while the host rewrites them between
 // replays. Each domain carries its own parity (which of its two lattices is
 // current) and the number of steps it takes in the current tick; launch k of
-// a tick advances the domains with k < stop_at.
+// a tick advances the domains with k < stop_at. When the tick's bulk runs as
+// launches of kmulti steps each (the strip kernel), these launches take the
+// remainder: a domain has taken stop_at / kmulti multi-step launches and
+// launch k advances it if k < stop_at mod kmulti.
 //
 // The per-cell arithmetic is the collide() of lbm_device.h, so a domain
 // stepped here is bit-identical to the same domain stepped alone.
@@ -24,18 +27,19 @@ namespace lbm {
 template <typename S, int BX>
 __global__ __launch_bounds__(BX) void batch_step_kernel(
     const BatchDomain *__restrict__ doms, const int2 *__restrict__ tiles,
-    const int *__restrict__ ntiles_dev, int k) {
+    const int *__restrict__ ntiles_dev, int k, int kmulti) {
   typedef typename Store<S>::C C;
   const int nt = *ntiles_dev;
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const int2 tile = tiles[t];
     const BatchDomain &d = doms[tile.x];
-    if (k >= d.stop_at) continue;
+    const int done = kmulti > 0 ? d.stop_at / kmulti : 0;  // multi-step launches taken
+    if (k >= d.stop_at - done * kmulti) continue;
     const int nx = d.nx, ny = d.ny;
     const int c = tile.y + threadIdx.x;
     if (c >= nx * ny) continue;
     const int y = c / nx, x = c - y * nx;
-    const int par = (d.parity + k) & 1;
+    const int par = (d.parity + done + k) & 1;
     const S *__restrict__ src = (const S *)d.lat[par];
     S *__restrict__ dst = (S *)d.lat[par ^ 1];
     const int xm = x == 0 ? nx - 1 : x - 1;
@@ -93,22 +97,42 @@ __global__ __launch_bounds__(BX) void batch_step_kernel(
 
 template <typename S>
 static hipError_t launch_batch_t(const BatchDomain *doms, const int2 *tiles,
-                                 const int *ntiles_dev, int grid, int k,
+                                 const int *ntiles_dev, int grid, int k, int kmulti,
                                  hipStream_t stream) {
   batch_step_kernel<S, BATCH_TILE><<<dim3(grid), dim3(BATCH_TILE), 0, stream>>>(
-      doms, tiles, ntiles_dev, k);
+      doms, tiles, ntiles_dev, k, kmulti);
   return hipGetLastError();
 }
 
 hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
-                        const int *ntiles_dev, int grid, int k,
+                        const int *ntiles_dev, int grid, int k, int kmulti,
                         hipStream_t stream) {
   switch (storage) {
-    case 0: return launch_batch_t<double>(doms, tiles, ntiles_dev, grid, k, stream);
-    case 1: return launch_batch_t<float>(doms, tiles, ntiles_dev, grid, k, stream);
-    case 2: return launch_batch_t<__half>(doms, tiles, ntiles_dev, grid, k, stream);
+    case 0: return launch_batch_t<double>(doms, tiles, ntiles_dev, grid, k, kmulti, stream);
+    case 1: return launch_batch_t<float>(doms, tiles, ntiles_dev, grid, k, kmulti, stream);
+    case 2: return launch_batch_t<__half>(doms, tiles, ntiles_dev, grid, k, kmulti, stream);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_multi(int storage, int k, int nw, const BatchDomain *doms,
+                              const int4 *items, const int *nitems, int grid, int j,
+                              hipStream_t stream) {
+  switch (storage) {
+    case 0: return launch_batch_multi_f64(k, nw, doms, items, nitems, grid, j, stream);
+    case 1: return launch_batch_multi_f32(k, nw, doms, items, nitems, grid, j, stream);
+    case 2: return launch_batch_multi_f16(k, nw, doms, items, nitems, grid, j, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+int batch_multi_per_cu(int storage, int k, int nw) {
+  switch (storage) {
+    case 0: return batch_multi_per_cu_f64(k, nw);
+    case 1: return batch_multi_per_cu_f32(k, nw);
+    case 2: return batch_multi_per_cu_f16(k, nw);
+  }
+  return 0;
 }
 
 }  // namespace lbm

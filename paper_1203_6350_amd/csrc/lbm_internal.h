@@ -84,9 +84,27 @@ struct BatchDomain {
   double dcf[3];
   double scale[9], inv_scale[9];
 };
+// One step (launch k of a tick) over the tile table. kmulti = 0: the tick
+// runs as one-step launches only; kmulti = K: the tick's bulk ran as K-step
+// launches and this launch takes step k of each member's remainder.
 hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
-                        const int *ntiles_dev, int grid, int k,
+                        const int *ntiles_dev, int grid, int k, int kmulti,
                         hipStream_t stream);
+// K = k steps (launch j of a tick) over the strip work items (int4: member,
+// first strip of the group, first row, rows), workgroups of nw waves.
+hipError_t launch_batch_multi(int storage, int k, int nw, const BatchDomain *doms,
+                              const int4 *items, const int *nitems, int grid, int j,
+                              hipStream_t stream);
+int batch_multi_per_cu(int storage, int k, int nw);
+hipError_t launch_batch_multi_f64(int k, int nw, const BatchDomain *doms, const int4 *items,
+                                  const int *nitems, int grid, int j, hipStream_t stream);
+hipError_t launch_batch_multi_f32(int k, int nw, const BatchDomain *doms, const int4 *items,
+                                  const int *nitems, int grid, int j, hipStream_t stream);
+hipError_t launch_batch_multi_f16(int k, int nw, const BatchDomain *doms, const int4 *items,
+                                  const int *nitems, int grid, int j, hipStream_t stream);
+int batch_multi_per_cu_f64(int k, int nw);
+int batch_multi_per_cu_f32(int k, int nw);
+int batch_multi_per_cu_f16(int k, int nw);
 
 // Von Neumann (lbm_vn.hip).
 struct VnParamsDev {

@@ -44,6 +44,10 @@ namespace lbm {
 // plane. Strips past the right edge repeat the last strip and store nothing,
 // so every wave of a workgroup runs the same number of rows and barriers.
 
+// Sponge form chosen per launch item at run time (the batched kernel, whose
+// members may each use another form); the other values are ChiMode.
+constexpr int CHI_RUNTIME = 4;
+
 template <int K>
 constexpr int strip_width() {
   return 64 - 2 * K;
@@ -131,6 +135,7 @@ struct StripCtx {
   int nx, ny, Y0, X0;
   C cx_chi;
   const C *chi_field, *chiy;
+  int chi_mode;        // ChiMode, read when CHI == CHI_RUNTIME
   C scale[9], inv_scale[9];
   CollideParams<C> p;
   C mref[9];
@@ -181,14 +186,17 @@ struct StripCtx {
   }
   // Sponge input of row r: the field value at this lane, or chi_y[r] of a
   // separable profile (combined with chi_x by chi_of when used).
+  __device__ __forceinline__ int mode() const { return CHI == CHI_RUNTIME ? chi_mode : CHI; }
   __device__ __forceinline__ C chi_raw(int r) const {
-    if (CHI == CHI_ZERO) return C(0);
-    if (CHI == CHI_FIELD) return chi_field[(int64_t)r * pitch + col];
+    const int m = mode();
+    if (m == CHI_ZERO) return C(0);
+    if (m == CHI_FIELD) return chi_field[(int64_t)r * pitch + col];
     return chiy[r];
   }
   __device__ __forceinline__ C chi_of(C raw) const {
-    if (CHI == CHI_SEP_MAX) return cx_chi > raw ? cx_chi : raw;
-    if (CHI == CHI_SEP_SUM) return cx_chi + raw;
+    const int m = mode();
+    if (m == CHI_SEP_MAX) return cx_chi > raw ? cx_chi : raw;
+    if (m == CHI_SEP_SUM) return cx_chi + raw;
     return raw;
   }
   // Loads of input row r (position Q).
@@ -273,59 +281,59 @@ struct StripCtx {
   }
 };
 
+// Lane geometry and launch constants of one strip: the wave's lane column,
+// the sponge's x part and the collision parameters.
 template <typename S, int VAR, int CHI, int K>
-__global__ __launch_bounds__(512) void step_multi_strip(
-    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
-    CollideParams<typename Store<S>::C> p,
-    const typename Store<S>::C *__restrict__ chi_field,
-    const typename Store<S>::C *__restrict__ chix,
-    const typename Store<S>::C *__restrict__ chiy, int rows_per_chunk,
-    int nstrips, int ngroups, int wg_per_xcd, int nwg) {
+__device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S *src, S *dst,
+                                            int nx, int ny, int64_t pitch, int64_t ps, int strip,
+                                            bool idle, int Y0, int nw,
+                                            const typename Store<S>::C *chi_field,
+                                            const typename Store<S>::C *chix,
+                                            const typename Store<S>::C *chiy, int chi_mode,
+                                            const typename Store<S>::C scale[9],
+                                            const typename Store<S>::C inv_scale[9],
+                                            const CollideParams<typename Store<S>::C> &p) {
   typedef typename Store<S>::C C;
   constexpr int W = strip_width<K>();
-  // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
-  // contiguous range of work (a band of chunk rows) so neighbouring strips
-  // and chunks share an L2
-  const int v = (blockIdx.x & 7) * wg_per_xcd + (blockIdx.x >> 3);
-  if (v >= nwg) return;
   const int lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
-  const int chunk = v / ngroups, group = v - chunk * ngroups;
-  int strip = group * nw + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const bool idle = strip >= nstrips;
-  if (idle) strip = nstrips - 1;
-  StripCtx<S, VAR, CHI, K> c;
   c.src = src;
   c.dst = dst;
-  c.ps = L.ps;
-  c.pitch = L.pitch;
-  c.nx = L.nx;
-  c.ny = L.ny;
+  c.ps = ps;
+  c.pitch = pitch;
+  c.nx = nx;
+  c.ny = ny;
   c.nw = nw;
   c.X0 = strip * W;
-  c.Y0 = chunk * rows_per_chunk;
-  const int R = min(rows_per_chunk, L.ny - c.Y0);  // output rows of the chunk
-  int col = (c.X0 - K + lane) % L.nx;
-  if (col < 0) col += L.nx;
+  c.Y0 = Y0;
+  int col = (c.X0 - K + lane) % nx;
+  if (col < 0) col += nx;
   c.col = (unsigned)col;
   c.col_bytes = (unsigned)col * (unsigned)sizeof(S);
   c.out_bytes = (unsigned)(lane - K) * (unsigned)sizeof(S);
-  c.store_lane = !idle && lane >= K && lane < K + W && c.X0 + lane - K < L.nx;
-  c.cx_chi = (CHI == CHI_SEP_MAX || CHI == CHI_SEP_SUM) ? chix[col] : C(0);
+  c.store_lane = !idle && lane >= K && lane < K + W && c.X0 + lane - K < nx;
+  c.chi_mode = chi_mode;
+  const int m = c.mode();
+  c.cx_chi = (m == CHI_SEP_MAX || m == CHI_SEP_SUM) ? chix[col] : C(0);
   c.chi_field = chi_field;
   c.chiy = chiy;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    c.scale[i] = L.scale[i];
-    c.inv_scale[i] = L.inv_scale[i];
+    c.scale[i] = scale[i];
+    c.inv_scale[i] = inv_scale[i];
   }
   c.p = p;
   if (VAR == V_I || VAR == V_II) ref_moments(p, c.mref);
+}
 
+// The row loop of one strip over R output rows from Y0 on.
+template <typename S, int VAR, int CHI, int K>
+__device__ __forceinline__ void strip_run(const StripCtx<S, VAR, CHI, K> &c, int R) {
+  typedef typename Store<S>::C C;
+  const int ny = c.ny;
   StripState<C, K> st;
   // Positions q = 0, 1, 2, 3 (rows Y0 - K .. Y0 - K + 3): step 1 starts at
   // q = 1, so row q = 0 supplies only {2, 5, 6}; {4, 7, 8} run two rows ahead.
-  auto next = [&](int rr) { return rr + 1 == L.ny ? 0 : rr + 1; };
+  auto next = [&](int rr) { return rr + 1 == ny ? 0 : rr + 1; };
   int r = c.wrap_row(c.Y0 - K);
   c.template load_256<0>(st, r);
   r = next(r);
@@ -378,6 +386,92 @@ __global__ __launch_bounds__(512) void step_multi_strip(
     LBM_STRIP_ITER(5)
   }
 #undef LBM_STRIP_ITER
+}
+
+template <typename S, int VAR, int CHI, int K>
+__global__ __launch_bounds__(512) void step_multi_strip(
+    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
+    CollideParams<typename Store<S>::C> p,
+    const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix,
+    const typename Store<S>::C *__restrict__ chiy, int rows_per_chunk,
+    int nstrips, int ngroups, int wg_per_xcd, int nwg) {
+  // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
+  // contiguous range of work (a band of chunk rows) so neighbouring strips
+  // and chunks share an L2
+  const int v = (blockIdx.x & 7) * wg_per_xcd + (blockIdx.x >> 3);
+  if (v >= nwg) return;
+  const int nw = blockDim.x >> 6;
+  const int chunk = v / ngroups, group = v - chunk * ngroups;
+  int strip = group * nw + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool idle = strip >= nstrips;
+  if (idle) strip = nstrips - 1;
+  const int Y0 = chunk * rows_per_chunk;
+  StripCtx<S, VAR, CHI, K> c;
+  strip_setup(c, src, dst, L.nx, L.ny, L.pitch, L.ps, strip, idle, Y0, nw, chi_field, chix, chiy,
+              CHI, L.scale, L.inv_scale, p);
+  strip_run(c, min(rows_per_chunk, L.ny - Y0));
+}
+
+// Batched form: a persistent grid walks a table of work items (member
+// domain, first strip of a strip group, first row, rows); each workgroup
+// runs the strip loop of its item with the member's own size, rates,
+// variant, sponge and parity. Launch j of a tick advances the members that
+// take at least (j + 1) K steps in it.
+template <typename S, int K>
+__global__ __launch_bounds__(512) void batch_multi_strip(const BatchDomain *__restrict__ doms,
+                                                         const int4 *__restrict__ items,
+                                                         const int *__restrict__ nitems_dev,
+                                                         int j) {
+  typedef typename Store<S>::C C;
+  const int nitems = *nitems_dev;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const int4 it = items[t];
+    const BatchDomain &d = doms[it.x];
+    if (j >= d.stop_at / K) continue;
+    const int nstrips = (d.nx + strip_width<K>() - 1) / strip_width<K>();
+    int strip = it.y + wave;
+    const bool idle = strip >= nstrips;
+    if (idle) strip = nstrips - 1;
+    const int par = (d.parity + j) & 1;
+    C scale[9], inv_scale[9];
+    CollideParams<C> p;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      scale[i] = C(d.scale[i]);
+      inv_scale[i] = C(d.inv_scale[i]);
+      p.s[i] = C(d.s[i]);
+    }
+    p.n = C(d.n);
+    p.m = C(d.m);
+    p.rho_b = C(d.rho_b);
+    p.ubx = C(d.ubx);
+    p.uby = C(d.uby);
+    p.dcf0 = C(d.dcf[0]);
+    p.dcf1 = C(d.dcf[1]);
+    p.dcf2 = C(d.dcf[2]);
+#define LBM_BATCH_RUN(VAR)                                                                   \
+  {                                                                                          \
+    StripCtx<S, VAR, CHI_RUNTIME, K> c;                                                      \
+    strip_setup(c, (const S *)d.lat[par], (S *)d.lat[par ^ 1], d.nx, d.ny, d.pitch, d.ps,   \
+                strip, idle, it.z, nw, (const C *)d.chi_field, (const C *)d.chi_x,           \
+                (const C *)d.chi_y, d.chi_mode, scale, inv_scale, p);                        \
+    strip_run(c, it.w);                                                                      \
+  }
+    switch (d.variant) {
+      case V_I: LBM_BATCH_RUN(V_I) break;
+      case V_II: LBM_BATCH_RUN(V_II) break;
+      case V_III: LBM_BATCH_RUN(V_III) break;
+      case V_VISC: LBM_BATCH_RUN(V_VISC) break;
+      default: LBM_BATCH_RUN(V_NONE) break;
+    }
+#undef LBM_BATCH_RUN
+    // the next item may belong to another member: no wave of this
+    // workgroup starts it before all have finished this one's rows
+    if (nw > 1) __builtin_amdgcn_s_barrier();
+  }
 }
 
 // Workgroups of the multi-step kernel that fit on the device at once, for
@@ -434,6 +528,31 @@ static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void
     case 4: return launch_multi_t<S, VAR, CHI, 4>(c, src, dst, stream);
   }
   return hipErrorInvalidValue;
+}
+
+template <typename S>
+hipError_t launch_batch_multi_storage(int k, int nw, const BatchDomain *doms, const int4 *items,
+                                      const int *nitems, int grid, int j, hipStream_t s) {
+  switch (k) {
+    case 2: batch_multi_strip<S, 2><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
+    case 3: batch_multi_strip<S, 3><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
+    case 4: batch_multi_strip<S, 4><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Workgroups of nw waves of the batched multi-step kernel resident per CU.
+template <typename S>
+int batch_multi_per_cu(int k, int nw) {
+  int per_cu = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (k) {
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 2>, 64 * nw, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 3>, 64 * nw, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 4>, 64 * nw, 0); break;
+  }
+  return e == hipSuccess ? per_cu : 0;
 }
 
 // All variants, sponge forms and step counts of one storage type.

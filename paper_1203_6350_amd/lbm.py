@@ -114,6 +114,8 @@ def load(path: str | None = None):
         "lbm_batch_step": [_H, i64],
         "lbm_batch_tick": [_H, i32, ctypes.POINTER(ctypes.c_int32)],
         "lbm_batch_set_grid": [_H, i32],
+        "lbm_batch_set_tuning": [_H, ctypes.POINTER(lbm_tuning)],
+        "lbm_batch_get_tuning": [_H, ctypes.POINTER(lbm_tuning)],
         "lbm_batch_set_members": [_H, ctypes.POINTER(_H), i32],
         "lbm_init_fields_dev": [_H, vp, vp, vp],
         "lbm_batch_sync": [_H],
@@ -472,6 +474,17 @@ def lbm_batch_tick(b, tick, member_steps=None):
     _check(load().lbm_batch_tick(b, int(tick), ms))
 
 
+def lbm_batch_set_tuning(b, kernel=4, block=64, nontemporal=0, rows=0):
+    t = lbm_tuning(int(kernel), int(block), int(nontemporal), int(rows))
+    _check(load().lbm_batch_set_tuning(b, ctypes.byref(t)))
+
+
+def lbm_batch_get_tuning(b):
+    t = lbm_tuning()
+    _check(load().lbm_batch_get_tuning(b, ctypes.byref(t)))
+    return t.as_dict()
+
+
 def lbm_batch_set_grid(b, blocks_per_cu):
     _check(load().lbm_batch_set_grid(b, int(blocks_per_cu)))
 
@@ -503,6 +516,12 @@ class Batch:
 
     def set_grid(self, blocks_per_cu):
         lbm_batch_set_grid(self.b, blocks_per_cu)
+
+    def set_tuning(self, **kw):
+        lbm_batch_set_tuning(self.b, **kw)
+
+    def tuning(self):
+        return lbm_batch_get_tuning(self.b)
 
     def sync(self):
         lbm_batch_sync(self.b)

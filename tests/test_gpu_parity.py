@@ -447,11 +447,11 @@ def batch_members(count, seed, storage="f32", max_n=96):
         nx = int(g.integers(1, max_n))
         ny = int(g.integers(1, max_n))
         rho, ux, uy, chi = random_case(nx, ny, seed * 1000 + k, u0=float(g.uniform(0, 0.05)))
-        var = ("none", "I", "II", "III")[k % 4]
+        var = ("none", "I", "II", "III", "visc")[k % 5]
         if var == "I":
             chi = np.minimum(chi, 0.1)
         q = (1.0, float(ux.mean()), 0.0)
-        kind = k % 3
+        kind = k % 4
         out.append(dict(nx=nx, ny=ny, rho=rho, ux=ux, uy=uy, chi=chi, q=q, variant=var,
                         kind=kind, ub=float(ux.mean()),
                         s=(0, 0, 0) + tuple(g.uniform(1.0, 1.95, 6))))
@@ -465,16 +465,29 @@ def make_member(m, storage):
         lat.set_sponge(m["chi"], m["q"])
     elif m["kind"] == 1:
         lat.set_sponge_separable(m["chi"].max(axis=0), m["chi"].max(axis=1), "max", m["q"])
+    elif m["kind"] == 2:
+        lat.set_sponge_separable(0.5 * m["chi"].max(axis=0), 0.5 * m["chi"].max(axis=1), "sum",
+                                 m["q"])
     else:
         lat.set_sponge(None, m["q"])
     return lat
 
 
+# batch launch shapes: the default (K-step strips), one-step tiles only, and
+# K-step strips of every K with several workgroup sizes and item heights
+BATCH_TUNINGS = [None, dict(kernel=0, block=256, rows=0), dict(kernel=2, block=128, rows=7),
+                 dict(kernel=3, block=512, rows=0), dict(kernel=4, block=64, rows=5),
+                 dict(kernel=4, block=256, rows=0)]
+
+
+@pytest.mark.parametrize("tuning", BATCH_TUNINGS)
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_batch_equals_alone_bitwise(storage):
-    """A member stepped in the batch (graph replays of the persistent launch,
-    with eager work between replays) is bit-identical to it stepped alone."""
-    say("case: batch vs alone", storage)
+def test_batch_equals_alone_bitwise(storage, tuning):
+    """A member stepped in the batch (graph replays of the persistent
+    launches, with eager work between replays) is bit-identical to it
+    stepped alone, in every batch launch shape (70 steps = whole K-step
+    launches plus one-step remainders)."""
+    say("case: batch vs alone", storage, tuning)
     members = batch_members(13, 5, storage)
     alone = []
     for m in members:
@@ -484,6 +497,9 @@ def test_batch_equals_alone_bitwise(storage):
         lat.close()
     lats = [make_member(m, storage) for m in members]
     b = lbm.Batch(lats)
+    if tuning is not None:
+        b.set_tuning(**tuning)
+    say("  batch shape", b.tuning())
     b.step(64)     # one graph of 64 launches
     b.sync()
     lats[0].diagnostics()  # eager work between replays
@@ -504,12 +520,16 @@ def test_batch_equals_alone_bitwise(storage):
         lat.close()
 
 
-def test_batch_tick_partial_steps_and_oracle():
+@pytest.mark.parametrize("tuning", [None, dict(kernel=0, block=256, rows=0),
+                                    dict(kernel=4, block=128, rows=3)])
+def test_batch_tick_partial_steps_and_oracle(tuning):
     """Members taking fewer steps than the tick keep their state; results match
     the oracle."""
     members = batch_members(6, 9, "f64", max_n=40)
     lats = [make_member(m, "f64") for m in members]
     b = lbm.Batch(lats)
+    if tuning is not None:
+        b.set_tuning(**tuning)
     steps = [5, 0, 12, 1, 12, 7]
     b.tick(12, steps)
     b.tick(12, steps)
@@ -520,6 +540,9 @@ def test_batch_tick_partial_steps_and_oracle():
             chi = m["chi"]
         elif m["kind"] == 1:
             chi = wl.sponge_2d(m["chi"].max(axis=0), m["chi"].max(axis=1))
+        elif m["kind"] == 2:
+            cx_, cy_ = 0.5 * m["chi"].max(axis=0), 0.5 * m["chi"].max(axis=1)
+            chi = cy_[:, None] + cx_[None, :]
         ref = oracle.step(oracle.feq_field(m["rho"], m["ux"], m["uy"]), 2 * st, s=m["s"], chi=chi,
                           qref=m["q"], variant=m["variant"])
         assert rel_max(lat.populations(), ref) <= 1e-12
