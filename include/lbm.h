@@ -267,8 +267,8 @@ int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu);
  * launches over 256-cell tiles only (block and rows ignored); kernel 2, 3
  * or 4 = that many steps per launch of the strip kernel, `block` threads per
  * workgroup (64, 128, 256 or 512: adjacent strips of one member), `rows`
- * rows per work item (1..4096, or 0 for a height at which the items about
- * fill the device once). Rebuilds the work-item table; synchronises the
+ * rows per work item (1..4096, or 0 for a height that gives about three
+ * items per resident workgroup). Default: K as above, block 64, rows 32. Rebuilds the work-item table; synchronises the
  * batch stream. Results are bit-identical for every shape. */
 int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t);
 int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t);

@@ -645,7 +645,7 @@ struct lbm_batch {
   // K-step strip launches (multi_k = 0: one-step tile launches only)
   int multi_k = 0;
   int multi_nw = 1;    // waves per workgroup
-  int multi_rows = 0;  // rows per work item, 0: fit the device
+  int multi_rows = 32; // rows per work item, 0: about three items per resident workgroup
   int multi_grid = 0;  // persistent workgroups of the strip kernel
   int4 *d_items = nullptr;
   int *d_nitems = nullptr;
@@ -780,9 +780,11 @@ int build_items(lbm_batch *b) {
     const int64_t ngroups = ((h->user.nx + W - 1) / W + nw - 1) / nw;
     group_rows += ngroups * h->user.ny;
   }
+  // automatic height: about three items per resident workgroup, so members
+  // of unequal size still balance over the persistent grid
+  const int64_t slots = 3 * (int64_t)b->multi_grid;
   const int64_t rows = b->multi_rows > 0 ? b->multi_rows
-                                         : std::max<int64_t>(1, (group_rows + b->multi_grid - 1) /
-                                                                    b->multi_grid);
+                                         : std::max<int64_t>(1, (group_rows + slots - 1) / slots);
   std::vector<int4> items;
   for (size_t i = 0; i < b->members.size(); ++i) {
     const lbm_handle *h = b->members[i];
