@@ -231,7 +231,9 @@ const char *lbm_last_error(void);
  * advances every member by K steps (the strip kernel over a table of work
  * items; K = 4 for FP32 storage, 3 for FP64 and FP16) and a member's
  * remainder of fewer than K steps in a tick runs as one-step launches over
- * a table of 256-cell tiles. All members must share the storage mode and the
+ * a table of 256-cell tiles. A batch whose work items do not fill the
+ * device once (few or small members) runs its ticks as one-step tile
+ * launches only, which spread it over the whole device. All members must share the storage mode and the
  * device. Each member's result is bit-identical to stepping it alone with
  * lbm_step.
  * While a batch has work in flight its members must not be used on their
@@ -272,6 +274,11 @@ int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu);
  * batch stream. Results are bit-identical for every shape. */
 int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t);
 int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t);
+
+/* Smallest number of strip work items for which a tick uses K-step launches
+ * (fewer: one-step tile launches only). -1 (default): the number of
+ * strip-kernel workgroups resident on the device at once; 0: always. */
+int lbm_batch_set_min_items(lbm_batch *b, int32_t min_items);
 
 int lbm_batch_sync(lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);

@@ -647,6 +647,7 @@ struct lbm_batch {
   int multi_nw = 1;    // waves per workgroup
   int multi_rows = 32; // rows per work item, 0: about three items per resident workgroup
   int multi_grid = 0;  // persistent workgroups of the strip kernel
+  int min_items = -1;  // strip launches need this many items (-1: multi_grid)
   int4 *d_items = nullptr;
   int *d_nitems = nullptr;
   int nitems = 0;
@@ -694,10 +695,9 @@ void free_graphs(lbm_batch *b) {
 // Instantiated graph of one tick: `nmulti` K-step strip launches
 // (j = 0 .. nmulti-1) then `nsingle` one-step tile launches (k = 0 ..
 // nsingle-1; with K-step launches these take the members' remainders).
-int batch_graph(lbm_batch *b, int nmulti, int nsingle, hipGraphExec_t *out) {
+int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, hipGraphExec_t *out) {
   const int grid = b->cus * b->blocks_per_cu;
-  const auto key = std::make_tuple(b->multi_k, nmulti, nsingle, b->blocks_per_cu,
-                                   b->multi_k ? b->multi_nw : 0);
+  const auto key = std::make_tuple(K, nmulti, nsingle, b->blocks_per_cu, K ? b->multi_nw : 0);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -706,11 +706,10 @@ int batch_graph(lbm_batch *b, int nmulti, int nsingle, hipGraphExec_t *out) {
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   hipError_t e = hipSuccess;
   for (int j = 0; j < nmulti && e == hipSuccess; ++j)
-    e = lbm::launch_batch_multi(b->storage, b->multi_k, b->multi_nw, b->d_doms, b->d_items,
+    e = lbm::launch_batch_multi(b->storage, K, b->multi_nw, b->d_doms, b->d_items,
                                 b->d_nitems, b->multi_grid, j, b->stream);
   for (int k = 0; k < nsingle && e == hipSuccess; ++k)
-    e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, b->multi_k,
-                          b->stream);
+    e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, K, b->stream);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -927,6 +926,13 @@ int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t) {
   return build_items(b);
 }
 
+int lbm_batch_set_min_items(lbm_batch *b, int32_t min_items) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (min_items < -1) return fail(LBM_EINVAL, "min_items must be -1 or >= 0");
+  b->min_items = min_items;
+  return LBM_OK;
+}
+
 int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t) {
   if (!b || !t) return fail(LBM_EINVAL, "NULL argument");
   t->kernel = b->multi_k;
@@ -957,20 +963,27 @@ int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
   HIP_TRY(hipMemcpyAsync(b->d_doms, hd, sizeof(lbm::BatchDomain) * n,
                          hipMemcpyHostToDevice, b->stream), "hipMemcpy(descriptors)");
   HIP_TRY(hipEventRecord(b->copied[sl], b->stream), "hipEventRecord");
-  // with K-step launches, member i takes st / K of them and then st mod K
-  // one-step launches; every launch flips its current lattice once
-  const int K = b->multi_k;
+  // K-step strip launches need enough work items to fill the persistent
+  // grid (each item marches its rows in sequence); a smaller batch runs as
+  // one-step tile launches, which spread it over the whole device. With
+  // K-step launches, member i takes st / K of them and then st mod K
+  // one-step launches; every launch flips its current lattice once. The
+  // graph holds tick / K K-step launches (members needing fewer skip the
+  // rest) and as many one-step launches as the largest remainder, so one
+  // tick length needs at most K graphs whatever the members' step counts.
+  const int need = b->min_items >= 0 ? b->min_items : b->multi_grid;
+  const int K = b->multi_k && b->nitems >= need ? b->multi_k : 0;
   int nmulti = 0, nsingle = tick;
   if (K) {
+    nmulti = tick / K;
     nsingle = 0;
     for (size_t i = 0; i < n; ++i) {
       const int st = member_steps ? member_steps[i] : tick;
-      nmulti = std::max(nmulti, st / K);
       nsingle = std::max(nsingle, st % K);
     }
   }
   hipGraphExec_t ex = nullptr;
-  int rc = batch_graph(b, nmulti, nsingle, &ex);
+  int rc = batch_graph(b, K, nmulti, nsingle, &ex);
   if (rc) return rc;
   HIP_TRY(hipGraphLaunch(ex, b->stream), "hipGraphLaunch");
   for (size_t i = 0; i < n; ++i) {

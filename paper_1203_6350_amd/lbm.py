@@ -116,6 +116,7 @@ def load(path: str | None = None):
         "lbm_batch_set_grid": [_H, i32],
         "lbm_batch_set_tuning": [_H, ctypes.POINTER(lbm_tuning)],
         "lbm_batch_get_tuning": [_H, ctypes.POINTER(lbm_tuning)],
+        "lbm_batch_set_min_items": [_H, i32],
         "lbm_batch_set_members": [_H, ctypes.POINTER(_H), i32],
         "lbm_init_fields_dev": [_H, vp, vp, vp],
         "lbm_batch_sync": [_H],
@@ -485,6 +486,10 @@ def lbm_batch_get_tuning(b):
     return t.as_dict()
 
 
+def lbm_batch_set_min_items(b, min_items):
+    _check(load().lbm_batch_set_min_items(b, int(min_items)))
+
+
 def lbm_batch_set_grid(b, blocks_per_cu):
     _check(load().lbm_batch_set_grid(b, int(blocks_per_cu)))
 
@@ -522,6 +527,13 @@ class Batch:
 
     def tuning(self):
         return lbm_batch_get_tuning(self.b)
+
+    def set_min_items(self, min_items):
+        lbm_batch_set_min_items(self.b, min_items)
+
+    def set_members(self, lattices):
+        lbm_batch_set_members(self.b, [m.h for m in lattices])
+        self.members = list(lattices)
 
     def sync(self):
         lbm_batch_sync(self.b)

@@ -499,6 +499,7 @@ def test_batch_equals_alone_bitwise(storage, tuning):
     b = lbm.Batch(lats)
     if tuning is not None:
         b.set_tuning(**tuning)
+    b.set_min_items(0)  # K-step launches even for this small batch
     say("  batch shape", b.tuning())
     b.step(64)     # one graph of 64 launches
     b.sync()
@@ -520,6 +521,31 @@ def test_batch_equals_alone_bitwise(storage, tuning):
         lat.close()
 
 
+def test_batch_small_batch_switches_to_tiles_bitwise():
+    """With the default threshold a batch of a few small members runs one-step
+    tile launches, a large member list K-step launches; switching between
+    them (membership changes between ticks) keeps every member bit-identical
+    to stepping it alone."""
+    members = batch_members(40, 21, "f32", max_n=120)
+    lats = [make_member(m, "f32") for m in members]
+    b = lbm.Batch(lats[:3])   # few items: tiles
+    b.step(9)
+    b.set_members(lats)       # 40 members, still below one device fill: tiles
+    b.set_min_items(0)        # force strips from here on
+    b.step(9)
+    b.set_min_items(-1)
+    b.step(5)
+    b.sync()
+    for k, (m, lat) in enumerate(zip(members, lats)):
+        ref = make_member(m, "f32")
+        ref.step(23 if k < 3 else 14)
+        np.testing.assert_array_equal(lat.save_state(), ref.save_state())
+        ref.close()
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
 @pytest.mark.parametrize("tuning", [None, dict(kernel=0, block=256, rows=0),
                                     dict(kernel=4, block=128, rows=3)])
 def test_batch_tick_partial_steps_and_oracle(tuning):
@@ -530,6 +556,7 @@ def test_batch_tick_partial_steps_and_oracle(tuning):
     b = lbm.Batch(lats)
     if tuning is not None:
         b.set_tuning(**tuning)
+    b.set_min_items(0)
     steps = [5, 0, 12, 1, 12, 7]
     b.tick(12, steps)
     b.tick(12, steps)
