@@ -314,21 +314,84 @@ def paper_pulse_leg(lbm, wl, steps=1200, every=20):
     return out
 
 
-def cpu_baseline(spec, fields, steps):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(spec, fields, steps, wl=None):
+    """The FP64 oracle, as it stands, on bounded samples of the workloads: the
+    headline (all host threads, and one thread for two steps), the 128^2
+    parity case, the 2048 x 1 row of the precision study and the smaller
+    batched domains."""
     import oracle
     rho, ux, uy = fields
-    f0 = oracle.feq_field(rho, ux, uy)
-    chi = spec.chi_2d()
     threads = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
-    oracle.step(f0, steps, s=spec.s, chi=chi, qref=spec.qref, variant=spec.variant,
-                nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": spec.nx * spec.ny * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.max_threads() if threads <= 0 else threads, "kind": "oracle",
-            "sample": "%dx%d workload, %d steps, Type %s, FP64, %.1f s" %
-                      (spec.nx, spec.ny, steps, spec.variant, dt)}
+
+    def run(f0, n, nthreads, **kw):
+        t0 = time.perf_counter()
+        oracle.step(f0, n, nthreads=nthreads, **kw)
+        return time.perf_counter() - t0
+
+    f0 = oracle.feq_field(rho, ux, uy)
+    kw = dict(s=spec.s, chi=spec.chi_2d(), qref=spec.qref, variant=spec.variant)
+    dt = run(f0, steps, threads, **kw)
+    dt1 = run(f0, 2, 1, **kw)
+    del f0
+    out = {"value": spec.nx * spec.ny * steps / dt / 1e6, "unit": "MLUPS",
+           "cores": threads, "kind": "oracle",
+           "sample": "%dx%d workload, %d steps, Type %s, FP64, %.1f s" %
+                     (spec.nx, spec.ny, steps, spec.variant, dt),
+           "single_thread_mlups": spec.nx * spec.ny * 2 / dt1 / 1e6,
+           "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "threads_used": threads,
+                    "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}}
+    if wl is not None:
+        c1 = wl.pulse_c1("II")
+        r1, u1, v1 = c1.fields()
+        t = run(oracle.feq_field(r1, u1, v1), c1.steps, threads, s=c1.s, chi=c1.chi_2d(),
+                qref=c1.qref, variant="II")
+        out["c1_128sq_fp64_1000_steps"] = {"mlups": c1.nx * c1.ny * c1.steps / t / 1e6, "s": t}
+        n3, steps3 = 2048, 4000
+        u0 = 0.1 * wl.CS
+        r3, u3, v3 = wl.plane_packet(n3, 1, amp=1e-4, centre=n3 / 2, u0=u0)
+        cx = wl.quadratic_ramp_1d(n3, 48, 0.2)
+        t = run(oracle.feq_field(r3, u3, v3), steps3, 1, chi=cx[None, :], qref=(1.0, u0, 0.0),
+                variant="II")
+        out["c3_2048x1_row_4000_steps"] = {"mlups": n3 * steps3 / t / 1e6, "s": t}
+        small = [d for d in wl.batch_c4() if d.nx <= 256]
+        cells, t = 0, 0.0
+        for d in small:
+            rr, uu, vv = d.fields()
+            t += run(oracle.feq_field(rr, uu, vv), 20, threads, s=d.s, chi=d.chi_2d(), qref=d.qref,
+                     variant=d.variant)
+            cells += d.nx * d.ny
+        out["c4_domains_n_le_256_20_steps"] = {"domains": len(small), "mlups": cells * 20 / t / 1e6,
+                                               "s": t}
+    return out
+
+
+def storages_leg(lbm, wl, torch, n, steps, warmup):
+    """The headline workload in FP64 and FP16 storage (autotuned launch shape)."""
+    out = {}
+    for st in ("f64", "f16"):
+        sp = wl.large_c2(variant="II", storage=st, n=n)
+        r = time_variant(lbm, wl, torch, sp, sp.fields(), steps, warmup)
+        eb = {"f64": 8, "f16": 2}[st]
+        cells = sp.nx * sp.ny
+        per = r["steps_per_launch"]
+        out[st] = {"mlups": r["mlups"], "tuning": r["tuning"], "steps_per_launch": per,
+                   "kernel_ms": r["kernel_ms"],
+                   "hbm_gbps": 18 * eb * cells / (r["kernel_ms"] * 1e-3) / 1e9,
+                   "alu_tflops": FLOPS_PER_UPDATE["II"] * cells * per / (r["kernel_ms"] * 1e-3) / 1e12,
+                   "single_step_equivalent_gbps": 18 * eb * r["mlups"] / 1e3,
+                   "nonfinite_cells": r["diag"][6]}
+    return out
 
 
 def main():
@@ -339,7 +402,8 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16"])
     ap.add_argument("--variants", default="II,I,III")
-    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-storages", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -437,6 +501,9 @@ def main():
     }
     if copy_gbps:
         out["roofline"]["hbm_frac_of_copy"] = hbm_gbps / copy_gbps
+    if not args.no_storages and args.storage == "f32":
+        print("bench: FP64 and FP16 storage", file=sys.stderr, flush=True)
+        out["storages"] = storages_leg(lbm, wl, torch, args.n, 400, 20)
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)
@@ -451,7 +518,7 @@ def main():
                                     warmup=args.serve_requests // 10)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(spec, fields, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(spec, fields, args.cpu_steps, wl)
     print(json.dumps(out), flush=True)
 
 
