@@ -66,6 +66,10 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   i64, ctypes.c_int]
         L.oracle_step.restype = ctypes.c_int
+        L.oracle_step_avg.argtypes = [i64, i64, dp, dp, dp, dp, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_double, i64,
+                                      ctypes.c_int]
+        L.oracle_step_avg.restype = ctypes.c_int
         L.oracle_collide.argtypes = [i64, dp, dp, dp, dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, dp]
         L.oracle_collide.restype = ctypes.c_int
@@ -142,6 +146,29 @@ def step(f, nsteps, *, s=S_MRT_DEFAULT, chi=None, qref=(1.0, 0.0, 0.0),
     if rc != 0:
         raise ValueError("oracle_step rejected its arguments")
     return f
+
+
+def step_avg(f, cf, nsteps, *, alpha, s=S_MRT_DEFAULT, chi=None, n=0.5, m=0.5, variant="II",
+             nthreads=0):
+    """Advance ``f[9][ny][nx]`` by ``nsteps`` steps with a time-averaged
+    reference state ``cf[3][ny][nx]`` = (rho^f, j^f_x, j^f_y): every step
+    collides with q_ref = (rho^f, j^f / rho^f), then c^f += alpha (c - c^f)
+    with the cell's pre-collision moments c (Sec. 1, Sec. 2.2).
+
+    Returns (f, cf), new arrays.
+    """
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    assert f.ndim == 3 and f.shape[0] == 9
+    ny, nx = f.shape[1:]
+    cf = np.array(np.broadcast_to(cf, (3, ny, nx)), dtype=np.float64, order="C", copy=True)
+    chi_a = None if chi is None else _f64(np.broadcast_to(chi, (ny, nx)))
+    sv = _f64(s)
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    rc = lib().oracle_step_avg(nx, ny, _dp(f), _dp(chi_a), _dp(cf), _dp(sv), float(n), float(m),
+                               v, float(alpha), int(nsteps), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_step_avg rejected its arguments")
+    return f, cf
 
 
 def collide(fin, *, s=S_MRT_DEFAULT, chi=0.0, qref=(1.0, 0.0, 0.0), n=0.5,

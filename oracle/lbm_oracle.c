@@ -278,6 +278,59 @@ int oracle_step(int64_t nx, int64_t ny, double *f, const double *chi,
   return 0;
 }
 
+/*
+ * oracle_step_avg -- like oracle_step with a time-dependent reference state
+ * (Sec. 1 and Sec. 2.2: q_ref may be a time-dependent mean of the
+ * macroscopic quantities). The mean is kept in conserved form:
+ *   cf : [3][ny][nx] (rho^f, j^f_x, j^f_y), updated in place.
+ * Each step, every cell collides with q_ref = (rho^f, j^f / rho^f), then the
+ * mean follows the cell's pre-collision moments c = (rho, j) as an
+ * exponential running mean, c^f <- c^f + alpha (c - c^f), before streaming.
+ * alpha = 0 keeps the field fixed.
+ */
+int oracle_step_avg(int64_t nx, int64_t ny, double *f, const double *chi, double *cf,
+                    const double *s, double n, double m, int variant, double alpha,
+                    int64_t nsteps, int nthreads) {
+  setup();
+  if (nx < 1 || ny < 1 || !f || !cf || !s || nsteps < 0) return -1;
+  const int64_t N = nx * ny;
+  double *post = (double *)malloc(sizeof(double) * Q * N);
+  if (!post) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  for (int64_t t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < ny; ++y) {
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t c = y * nx + x;
+        double fin[Q], fo[Q], mom[Q];
+        for (int i = 0; i < Q; ++i) fin[i] = f[i * N + c];
+        const double rf = cf[c], jxf = cf[N + c], jyf = cf[2 * N + c];
+        collide_cell(fin, chi ? chi[c] : 0.0, rf, jxf / rf, jyf / rf, s, n, m, variant, fo);
+        for (int i = 0; i < Q; ++i) post[i * N + c] = fo[i];
+        matvec(M_D2Q9, fin, mom);  /* pre-collision moments: rho = mom[0], j = mom[1..2] */
+        cf[c] = rf + alpha * (mom[0] - rf);
+        cf[N + c] = jxf + alpha * (mom[1] - jxf);
+        cf[2 * N + c] = jyf + alpha * (mom[2] - jyf);
+      }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < ny; ++y) {
+      for (int64_t x = 0; x < nx; ++x) {
+        for (int i = 0; i < Q; ++i) {
+          const int64_t xs = wrap(x - CX[i], nx), ys = wrap(y - CY[i], ny);
+          f[i * N + y * nx + x] = post[i * N + ys * nx + xs];
+        }
+      }
+    }
+  }
+  free(post);
+  return 0;
+}
+
 /* One collision (no streaming) for a batch of independent cells, used by the
  * Von Neumann cross-checks.  fin, fout: [ncell][9]. */
 int oracle_collide(int64_t ncell, const double *fin, const double *chi,

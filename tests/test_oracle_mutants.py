@@ -36,6 +36,10 @@ MUTANTS = {
     "velocity_from_wrong_row": ("CY[j] = (int)M_D2Q9[2][j];", "CY[j] = (int)M_D2Q9[6][j] / -2;"),
     "none_keeps_shift": ("if (variant == V_NONE || variant == V_VISC) chi = 0.0;", "if (variant == V_VISC) chi = 0.0;"),
     "visc_ramp_wrong_end": ("sk[k] = s[k] + (1.0 - s[k]) * xi;", "sk[k] = s[k] + (2.0 - s[k]) * xi;"),
+    "mean_from_post_collision": ("matvec(M_D2Q9, fin, mom);  /* pre-collision", "matvec(M_D2Q9, fo, mom);  /* pre-collision"),
+    "mean_rate_complement": ("cf[c] = rf + alpha * (mom[0] - rf);", "cf[c] = rf + (1.0 - alpha) * (mom[0] - rf);"),
+    "mean_momentum_component": ("cf[2 * N + c] = jyf + alpha * (mom[2] - jyf);", "cf[2 * N + c] = jyf + alpha * (mom[1] - jyf);"),
+    "mean_velocity_not_momentum": ("rf, jxf / rf, jyf / rf, s, n, m, variant, fo);", "rf, jxf, jyf, s, n, m, variant, fo);"),
 }
 
 

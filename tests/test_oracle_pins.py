@@ -452,3 +452,84 @@ def test_viscosity_ramp_limits():
         sk = S[k] + (1 - S[k]) * xi
         np.testing.assert_allclose(m_out[:, k] - meq[:, k], (1 - sk) * (m_in[:, k] - meq[:, k]),
                                    rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------ time-averaged reference state (Sec. 1, Sec. 2.2)
+
+def _conserved(f):
+    rho, ux, uy = oracle.moments(f)
+    return np.stack([rho, rho * ux, rho * uy])
+
+
+def _qref_field(cf):
+    return np.stack([cf[0], cf[1] / cf[0], cf[2] / cf[0]])
+
+
+def test_averaged_reference_alpha_zero_is_static_field():
+    """alpha = 0 keeps the mean fixed: the averaged stepper equals the static
+    per-cell reference stepper (up to the rounding of u^f = j^f / rho^f)."""
+    f = random_state(11, 9, 52)
+    g = np.random.default_rng(53)
+    cf = np.stack([1 + 1e-3 * g.standard_normal((9, 11)), 0.05 + 1e-3 * g.standard_normal((9, 11)),
+                   1e-3 * g.standard_normal((9, 11))])
+    chi = g.uniform(0, 0.4, (9, 11))
+    for var in ("I", "II", "III"):
+        c_ = np.minimum(chi, 0.1) if var == "I" else chi
+        a, cf_out = oracle.step_avg(f, cf, 6, alpha=0.0, chi=c_, variant=var)
+        b = oracle.step(f, 6, chi=c_, qref_field=_qref_field(cf), variant=var)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+        np.testing.assert_array_equal(cf_out, cf)
+
+
+def test_averaged_reference_without_sponge_is_running_mean_of_moments():
+    """With chi = 0 the reference never enters the step: populations are those
+    of the plain scheme bit for bit, and the mean is the exponential running
+    mean of the cell's pre-collision moments over the step history."""
+    f = random_state(10, 12, 54)
+    cf0 = _conserved(f) * 0.9
+    alpha = 0.3
+    a, cf = oracle.step_avg(f, cf0, 8, alpha=alpha, chi=0.0, variant="II")
+    np.testing.assert_array_equal(a, oracle.step(f, 8, chi=0.0, variant="II"))
+    mean, ft = cf0.copy(), f
+    for _ in range(8):
+        mean = (1 - alpha) * mean + alpha * _conserved(ft)
+        ft = oracle.step(ft, 1, chi=0.0, variant="II")
+    np.testing.assert_allclose(cf, mean, rtol=0, atol=1e-14)
+
+
+def test_averaged_reference_equals_static_steps_plus_mean_update():
+    """With a sponge, each averaged step is one static-reference step with the
+    current mean, followed by the mean update from the pre-collision
+    moments; checked for every variant and several rates."""
+    f = random_state(9, 8, 55)
+    g = np.random.default_rng(56)
+    chi = g.uniform(0, 0.3, (8, 9))
+    for var in ("I", "II", "III", "none"):
+        c_ = np.minimum(chi, 0.1) if var == "I" else chi
+        for alpha in (0.05, 0.5, 1.0):
+            cf0 = _conserved(f) + 1e-4 * g.standard_normal((3, 8, 9))
+            a, cf = oracle.step_avg(f, cf0, 5, alpha=alpha, chi=c_, variant=var)
+            ft, mean = f, cf0.copy()
+            for _ in range(5):
+                nxt = oracle.step(ft, 1, chi=c_, qref_field=_qref_field(mean), variant=var)
+                mean = mean + alpha * (_conserved(ft) - mean)
+                ft = nxt
+            np.testing.assert_allclose(a, ft, rtol=0, atol=1e-14)
+            np.testing.assert_allclose(cf, mean, rtol=0, atol=1e-14)
+
+
+def test_averaged_reference_equilibrium_is_fixed_point():
+    """A uniform equilibrium whose mean equals its own state stays fixed for
+    every variant, rate and sponge."""
+    n = 7
+    rho = np.full((n, n), 1.01)
+    ux = np.full((n, n), 0.06)
+    uy = np.full((n, n), -0.02)
+    f0 = oracle.feq_field(rho, ux, uy)
+    cf0 = np.stack([rho, rho * ux, rho * uy])
+    chi = np.random.default_rng(57).uniform(0, 0.5, (n, n))
+    for var in ("I", "II", "III"):
+        a, cf = oracle.step_avg(f0, cf0, 10, alpha=0.2, chi=np.minimum(chi, 0.1) if var == "I"
+                                else chi, variant=var)
+        np.testing.assert_allclose(a, f0, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(cf, cf0, rtol=0, atol=1e-15)
