@@ -189,6 +189,32 @@ int lbm_load_state(lbm_handle *h, const void *host, size_t bytes);
 
 int lbm_get_info(lbm_handle *h, lbm_info *info);
 
+/* ---- per-cell and time-averaged reference state ----------------------
+ * The paper lets q_ref depend on space and time: a far field, or a
+ * time-dependent mean of the macroscopic quantities (Sec. 1, eq. eq:sponge;
+ * Sec. 2.2, eq. eq:reff and the discussion after it).
+ *
+ * lbm_set_qref_field: per-cell reference state, host [ny][nx] arrays
+ * (rho_f > 0, all finite), copied to the device as the conserved moments
+ * (rho^f, rho^f u^f) in the compute precision; it replaces the uniform q_ref
+ * of lbm_set_sponge until cleared with three NULL arrays (which also sets
+ * the averaging rate back to 0). While a field is set, lbm_step runs the
+ * one-cell-per-thread kernel whatever the tuning, the handle cannot join a
+ * batch, and the field is not part of lbm_save_state (read it with
+ * lbm_get_qref_field).
+ *
+ * lbm_set_qref_average: after each step's collision the field follows the
+ * cell's pre-collision conserved moments c = (rho, j) as an exponential
+ * running mean, c^f <- c^f + alpha (c - c^f), alpha in [0, 1] (0: fixed
+ * field, the default). Needs a field (LBM_ESTATE otherwise).
+ *
+ * lbm_get_qref_field: the current field as (rho^f, u^f = j^f / rho^f),
+ * host [ny][nx]; synchronises. */
+int lbm_set_qref_field(lbm_handle *h, const double *rho_f, const double *ux_f,
+                       const double *uy_f);
+int lbm_set_qref_average(lbm_handle *h, double alpha);
+int lbm_get_qref_field(lbm_handle *h, double *rho_f, double *ux_f, double *uy_f);
+
 /* ---- kernel tuning ----------------------------------------------------
  * Launch shape of the step kernel. Every choice computes the same per-cell
  * arithmetic, so results are bit-identical across tunings. */

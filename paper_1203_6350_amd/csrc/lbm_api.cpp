@@ -73,6 +73,9 @@ struct lbm_handle {
   void *chi_field = nullptr;  // compute type [ny][pitch]
   void *chi_x = nullptr;      // compute type [nx]
   void *chi_y = nullptr;      // compute type [ny]
+  void *qf = nullptr;         // compute type [3][qps]: per-cell reference, or NULL
+  int64_t qps = 0;
+  double qalpha = 0.0;        // running-mean rate of the reference
   double *diag_partials = nullptr;
   double *diag_out = nullptr;
   int64_t steps = 0;
@@ -134,6 +137,9 @@ void fill_cfg(lbm_handle *h) {
   s.chi_field = h->chi_field;
   s.chi_x = h->chi_x;
   s.chi_y = h->chi_y;
+  s.qfield = h->qf;
+  s.qps = h->qps;
+  s.qalpha = h->qf ? h->qalpha : 0.0;
 }
 
 // Upload an FP64 host array converted to the compute type of the handle.
@@ -371,7 +377,8 @@ int lbm_step(lbm_handle *h, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   int64_t k = 0;
   const int per = h->cfg.kernel;  // time steps per launch of the multi-step kernel
-  if (per >= lbm::KERNEL_MULTI_MIN) {
+  // a per-cell reference state runs in the one-step kernel only
+  if (per >= lbm::KERNEL_MULTI_MIN && !h->qf) {
     while (n - k >= 2) {
       const int m = n - k >= per ? per : (int)(n - k);
       hipError_t e = lbm::launch_multi_steps(h->cfg, m, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
@@ -603,6 +610,7 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
 void lbm_destroy(lbm_handle *h) {
   if (!h) return;
   free_sponge(h);
+  if (h->qf) (void)hipFreeAsync(h->qf, h->stream);
   if (h->diag_partials) (void)hipFreeAsync(h->diag_partials, h->stream);
   if (h->diag_out) (void)hipFreeAsync(h->diag_out, h->stream);
   if (h->own_lat) {
@@ -611,6 +619,84 @@ void lbm_destroy(lbm_handle *h) {
       if (h->lat[k]) (void)hipFree(h->lat[k]);
   }
   delete h;
+}
+
+int lbm_set_qref_field(lbm_handle *h, const double *rho_f, const double *ux_f,
+                       const double *uy_f) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!rho_f && !ux_f && !uy_f) {
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (h->qf) (void)hipFreeAsync(h->qf, h->stream);
+    h->qf = nullptr;
+    h->qalpha = 0.0;
+    fill_cfg(h);
+    return LBM_OK;
+  }
+  if (!rho_f || !ux_f || !uy_f) return fail(LBM_EINVAL, "give all three reference fields or none");
+  const int64_t nx = h->user.nx, ny = h->user.ny, pitch = h->cfg.pitch;
+  for (int64_t c = 0; c < nx * ny; ++c)
+    if (!(rho_f[c] > 0) || !is_fin(rho_f[c]) || !is_fin(ux_f[c]) || !is_fin(uy_f[c]))
+      return fail(LBM_EINVAL, "reference fields must be finite with rho_f > 0");
+  // conserved moments as deviations from the base, formed in FP64 without
+  // cancellation: d j = (rho^f - rho_b) u^f + rho_b (u^f - u_b)
+  const double rb = h->user.rho_base, ubx = h->user.ux_base, uby = h->user.uy_base;
+  const int64_t qps = round_up(ny * pitch, 64);
+  std::vector<double> host((size_t)(3 * qps), 0.0);
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      const int64_t c = y * nx + x, d = y * pitch + x;
+      const double dr = rho_f[c] - rb;
+      host[(size_t)d] = dr;
+      host[(size_t)(qps + d)] = dr * ux_f[c] + rb * (ux_f[c] - ubx);
+      host[(size_t)(2 * qps + d)] = dr * uy_f[c] + rb * (uy_f[c] - uby);
+    }
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (h->qf && h->qps != qps) {
+    (void)hipFreeAsync(h->qf, h->stream);
+    h->qf = nullptr;
+  }
+  h->qps = qps;
+  int rc = upload_compute(h, host.data(), host.size(), &h->qf);
+  if (rc) return rc;
+  fill_cfg(h);
+  return LBM_OK;
+}
+
+int lbm_get_qref_field(lbm_handle *h, double *rho_f, double *ux_f, double *uy_f) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h->qf) return fail(LBM_ESTATE, "no per-cell reference state is set");
+  if (!rho_f || !ux_f || !uy_f) return fail(LBM_EINVAL, "output arrays are NULL");
+  const bool f64 = h->user.storage == LBM_STORAGE_F64;
+  const size_t n = (size_t)(3 * h->qps);
+  std::vector<double> host(n);
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (f64) {
+    HIP_TRY(hipMemcpy(host.data(), h->qf, n * 8, hipMemcpyDeviceToHost), "hipMemcpy(reference)");
+  } else {
+    std::vector<float> tmp(n);
+    HIP_TRY(hipMemcpy(tmp.data(), h->qf, n * 4, hipMemcpyDeviceToHost), "hipMemcpy(reference)");
+    for (size_t i = 0; i < n; ++i) host[i] = tmp[i];
+  }
+  const double rb = h->user.rho_base, ubx = h->user.ux_base, uby = h->user.uy_base;
+  const int64_t nx = h->user.nx, ny = h->user.ny, pitch = h->cfg.pitch, qps = h->qps;
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      const int64_t c = y * nx + x, d = y * pitch + x;
+      const double rho = rb + host[(size_t)d];
+      rho_f[c] = rho;
+      ux_f[c] = (rb * ubx + host[(size_t)(qps + d)]) / rho;
+      uy_f[c] = (rb * uby + host[(size_t)(2 * qps + d)]) / rho;
+    }
+  return LBM_OK;
+}
+
+int lbm_set_qref_average(lbm_handle *h, double alpha) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(LBM_EINVAL, "alpha must lie in [0, 1]");
+  if (!h->qf) return fail(LBM_ESTATE, "set a per-cell reference state first");
+  h->qalpha = alpha;
+  fill_cfg(h);
+  return LBM_OK;
 }
 
 int lbm_init_fields_dev(lbm_handle *h, const double *rho, const double *ux,
@@ -760,6 +846,8 @@ int validate_members(lbm_handle *const *members, int32_t count) {
       return fail(LBM_EINVAL, "all members must live on one device");
     for (int32_t j = 0; j < i; ++j)
       if (members[j] == members[i]) return fail(LBM_EINVAL, "members must be distinct");
+    if (members[i]->qf)
+      return fail(LBM_EINVAL, "members with a per-cell reference state are not batched");
   }
   return LBM_OK;
 }

@@ -29,6 +29,11 @@ struct StepConfig {
   int block;             // threads per block: 64, 128, 256 or 512
   int nontemporal;       // 1: streaming (non-temporal) stores (vector kernel)
   int rows;              // rows per chunk of the multi-step kernel (0: fit the device)
+  // per-cell reference state: three planes [3][qps] of (d rho^f, d j^f_x,
+  // d j^f_y), each [ny][pitch], compute type; NULL: uniform dcf above
+  void *qfield;
+  int64_t qps;
+  double qalpha;         // running-mean rate of the reference (0: fixed)
 };
 
 enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MAX = 4 };

@@ -166,6 +166,80 @@ __global__ __launch_bounds__(BX) void step_vec(
   for (int i = 0; i < 9; ++i) store16<NT>(dst + i * ps + r0 + x0, out[i]);
 }
 
+// One step with a per-cell reference state (the paper lets q_ref depend on
+// space and time: a far field, or a time-dependent mean of the macroscopic
+// quantities, Sec. 1 and Sec. 2.2). qf holds three planes, qps elements
+// apart, of the reference's conserved moments as deviations from the base,
+// (d rho^f, d j^f_x, d j^f_y), each [ny][pitch]. The cell's reference moments
+// dm^ref = m^eq(c^f) - m^eq(c_b) are formed per cell. With alpha != 0 the
+// reference then follows the cell's pre-collision conserved moments as an
+// exponential running mean, c^f <- c^f + alpha (c - c^f), in place (every
+// cell reads and writes only its own entry).
+template <typename S, int VAR, int CHI>
+__global__ __launch_bounds__(256) void step_qfield(
+    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
+    CollideParams<typename Store<S>::C> p,
+    const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix,
+    const typename Store<S>::C *__restrict__ chiy,
+    typename Store<S>::C *__restrict__ qf, int64_t qps, typename Store<S>::C alpha) {
+  typedef typename Store<S>::C C;
+  const int bpr = (L.nx + 255) / 256;
+  const int y = blockIdx.x / bpr;
+  const int x = (blockIdx.x - y * bpr) * 256 + threadIdx.x;
+  if (x >= L.nx) return;
+  const int xm = x == 0 ? L.nx - 1 : x - 1;
+  const int xp = x == L.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? L.ny - 1 : y - 1;
+  const int yp = y == L.ny - 1 ? 0 : y + 1;
+  const int64_t r0 = (int64_t)y * L.pitch, rm = (int64_t)ym * L.pitch,
+                rp = (int64_t)yp * L.pitch;
+  const int64_t ps = L.ps;
+  C g[9];
+  g[0] = Store<S>::load(src + 0 * ps + r0 + x, L.scale[0]);
+  g[1] = Store<S>::load(src + 1 * ps + r0 + xm, L.scale[1]);
+  g[2] = Store<S>::load(src + 2 * ps + rm + x, L.scale[2]);
+  g[3] = Store<S>::load(src + 3 * ps + r0 + xp, L.scale[3]);
+  g[4] = Store<S>::load(src + 4 * ps + rp + x, L.scale[4]);
+  g[5] = Store<S>::load(src + 5 * ps + rm + xm, L.scale[5]);
+  g[6] = Store<S>::load(src + 6 * ps + rm + xp, L.scale[6]);
+  g[7] = Store<S>::load(src + 7 * ps + rp + xp, L.scale[7]);
+  g[8] = Store<S>::load(src + 8 * ps + rp + xm, L.scale[8]);
+  const int64_t cell = r0 + x;
+  const C chi = chi_at<C, CHI>(chi_field, chix, chiy, cell, x, y);
+  CollideParams<C> pc = p;
+  pc.dcf0 = qf[cell];
+  pc.dcf1 = qf[qps + cell];
+  pc.dcf2 = qf[2 * qps + cell];
+  // pre-collision conserved moments (rows 0-2 of M)
+  const C dr = g[0] + ((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
+  const C djx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
+  const C djy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+  C mref[9];
+  if (VAR == V_I || VAR == V_II) ref_moments(pc, mref);
+  collide<C, VAR>(g, chi, pc, mref);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Store<S>::store(dst + i * ps + r0 + x, g[i], L.inv_scale[i]);
+  if (alpha != C(0)) {
+    qf[cell] = fmaC(alpha, dr - pc.dcf0, pc.dcf0);
+    qf[qps + cell] = fmaC(alpha, djx - pc.dcf1, pc.dcf1);
+    qf[2 * qps + cell] = fmaC(alpha, djy - pc.dcf2, pc.dcf2);
+  }
+}
+
+template <typename S, int VAR, int CHI>
+static hipError_t launch_qfield(const StepConfig &c, const void *src, void *dst,
+                                hipStream_t stream) {
+  typedef typename Store<S>::C C;
+  Lat<S> L = make_lat<S>(c);
+  CollideParams<C> p = make_params<C>(c);
+  const int64_t blocks = (int64_t)((c.nx + 255) / 256) * c.ny;
+  step_qfield<S, VAR, CHI><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(
+      (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
+      (const C *)c.chi_y, (C *)c.qfield, c.qps, C(c.qalpha));
+  return hipGetLastError();
+}
+
 template <typename S, int VAR, int CHI, int BX>
 static hipError_t launch_generic(const StepConfig &c, const void *src, void *dst,
                                  hipStream_t stream) {
@@ -203,6 +277,7 @@ bool vec_supported(const StepConfig &c) {
 template <typename S, int VAR, int CHI>
 static hipError_t launch_step_t(const StepConfig &c, const void *src,
                                 void *dst, hipStream_t stream) {
+  if (c.qfield) return launch_qfield<S, VAR, CHI>(c, src, dst, stream);
   const int kernel = c.kernel == KERNEL_VEC && vec_supported(c) ? KERNEL_VEC : KERNEL_GENERIC;
   if (kernel == KERNEL_GENERIC) {
     switch (c.block) {

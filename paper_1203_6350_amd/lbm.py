@@ -102,6 +102,9 @@ def load(path: str | None = None):
         "lbm_set_populations": [_H, _DP],
         "lbm_get_info": [_H, ctypes.POINTER(lbm_info)],
         "lbm_set_tuning": [_H, ctypes.POINTER(lbm_tuning)],
+        "lbm_set_qref_field": [_H, _DP, _DP, _DP],
+        "lbm_set_qref_average": [_H, ctypes.c_double],
+        "lbm_get_qref_field": [_H, _DP, _DP, _DP],
         "lbm_get_tuning": [_H, ctypes.POINTER(lbm_tuning)],
         "lbm_autotune": [_H, i32, ctypes.POINTER(lbm_tuning), _DP],
         "lbm_state_bytes": [_H, ctypes.POINTER(sz)],
@@ -247,6 +250,29 @@ def lbm_get_info(h):
     info = lbm_info()
     _check(load().lbm_get_info(h, ctypes.byref(info)))
     return info
+
+
+def lbm_set_qref_field(h, rho_f=None, ux_f=None, uy_f=None):
+    """Per-cell reference state (host arrays [ny][nx]); all None clears it."""
+    info = lbm_get_info(h) if rho_f is not None else None
+    n = None if info is None else info.nx * info.ny
+    _r, pr = _host(rho_f, n)
+    _u, pu = _host(ux_f, n)
+    _v, pv = _host(uy_f, n)
+    _check(load().lbm_set_qref_field(h, pr, pu, pv))
+
+
+def lbm_set_qref_average(h, alpha):
+    _check(load().lbm_set_qref_average(h, float(alpha)))
+
+
+def lbm_get_qref_field(h):
+    info = lbm_get_info(h)
+    shape = (info.ny, info.nx)
+    rho, ux, uy = (np.empty(shape) for _ in range(3))
+    _check(load().lbm_get_qref_field(h, rho.ctypes.data_as(_DP), ux.ctypes.data_as(_DP),
+                                     uy.ctypes.data_as(_DP)))
+    return rho, ux, uy
 
 
 def lbm_moments(h):
@@ -399,6 +425,15 @@ class Lattice:
 
     def moments(self):
         return lbm_moments(self.h)
+
+    def set_qref_field(self, rho_f=None, ux_f=None, uy_f=None):
+        lbm_set_qref_field(self.h, rho_f, ux_f, uy_f)
+
+    def set_qref_average(self, alpha):
+        lbm_set_qref_average(self.h, alpha)
+
+    def qref_field(self):
+        return lbm_get_qref_field(self.h)
 
     def diagnostics(self):
         return lbm_diagnostics(self.h)

@@ -344,9 +344,10 @@ TUNINGS = [dict(kernel=k, block=b, nontemporal=nt, rows=0) for k in (0, 1)
 # last strips are padding on every size below)
 TUNINGS += [dict(kernel=2, block=b, nontemporal=0, rows=r) for b in (64, 128, 256, 512)
             for r in (0, 1, 5, 7, 8, 16, 32, 48)]
-# three and four steps per launch (their own halo widths and loop phases)
-TUNINGS += [dict(kernel=k, block=b, nontemporal=0, rows=r) for k in (3, 4) for b in (64, 512)
-            for r in (0, 1, 5, 8, 16, 32)]
+# three and four steps per launch (their own halo widths and loop phases);
+# together with the lists above this holds every autotuner candidate
+TUNINGS += [dict(kernel=k, block=b, nontemporal=0, rows=r) for k in (3, 4)
+            for b in (64, 128, 256, 512) for r in (0, 1, 5, 8, 16, 32)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])

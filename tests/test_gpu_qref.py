@@ -1,0 +1,168 @@
+"""Per-cell and time-averaged reference state on the GPU against the oracle
+(the paper's q_ref as a function of space and time: Sec. 1, Sec. 2.2)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1203_6350_amd import lbm, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    lbm.load()
+    yield
+
+
+def case(nx, ny, seed, u0=0.04):
+    g = np.random.default_rng(seed)
+    rho = 1 + 1e-3 * g.standard_normal((ny, nx))
+    ux = u0 + 1e-3 * g.standard_normal((ny, nx))
+    uy = 1e-3 * g.standard_normal((ny, nx))
+    chi = g.uniform(0, 0.4, (ny, nx)) * (g.uniform(size=(ny, nx)) < 0.6)
+    rf = 1 + 5e-4 * g.standard_normal((ny, nx))
+    uxf = u0 + 5e-4 * g.standard_normal((ny, nx))
+    uyf = 5e-4 * g.standard_normal((ny, nx))
+    return rho, ux, uy, chi, (rf, uxf, uyf)
+
+
+def rel_max(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def conserved(q):
+    rf, uxf, uyf = q
+    return np.stack([rf, rf * uxf, rf * uyf])
+
+
+@pytest.mark.parametrize("variant", ["I", "II", "III", "none", "visc"])
+@pytest.mark.parametrize("alpha", [0.0, 0.02, 1.0])
+def test_reference_field_fp64_against_oracle(variant, alpha):
+    """FP64: populations within 1e-12 of max |f| and the reference field
+    within 1e-12 of the oracle after 30 steps (ragged 77 x 45, 2-D sponge)."""
+    nx, ny, T = 77, 45, 30
+    say("case: reference field FP64", variant, alpha)
+    rho, ux, uy, chi, q = case(nx, ny, 3 + len(variant))
+    if variant == "I":
+        chi = np.minimum(chi, 0.1)
+    if variant == "visc":
+        chi = np.minimum(chi, 1.0)
+    f0 = oracle.feq_field(rho, ux, uy)
+    ref, cf = oracle.step_avg(f0, conserved(q), T, alpha=alpha, chi=chi, variant=variant)
+    lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage="f64", variant=variant, ux_base=0.04)
+    lat.set_sponge(chi, (1.0, 0.04, 0.0))
+    lat.set_qref_field(*q)
+    if alpha:
+        lat.set_qref_average(alpha)
+    lat.step(T)
+    got = lat.populations()
+    rf, uxf, uyf = lat.qref_field()
+    lat.close()
+    assert rel_max(got, ref) <= 1e-12
+    np.testing.assert_allclose(rf, cf[0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(rf * uxf, cf[1], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(rf * uyf, cf[2], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("form", ["max", "sum", "zero"])
+def test_reference_field_with_separable_sponge_fp64(form):
+    nx, ny, T = 64, 50, 25
+    rho, ux, uy, chi, q = case(nx, ny, 17)
+    g = np.random.default_rng(18)
+    cx = g.uniform(0, 0.2, nx)
+    cy = g.uniform(0, 0.2, ny)
+    chi2 = (np.maximum(cy[:, None], cx[None, :]) if form == "max" else
+            cy[:, None] + cx[None, :] if form == "sum" else np.zeros((ny, nx)))
+    f0 = oracle.feq_field(rho, ux, uy)
+    ref, _ = oracle.step_avg(f0, conserved(q), T, alpha=0.1, chi=chi2, variant="II")
+    lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage="f64", variant="II", ux_base=0.04)
+    if form == "zero":
+        lat.set_sponge(None, (1.0, 0.04, 0.0))
+    else:
+        lat.set_sponge_separable(cx, cy, form, (1.0, 0.04, 0.0))
+    lat.set_qref_field(*q)
+    lat.set_qref_average(0.1)
+    lat.step(T)
+    got = lat.populations()
+    lat.close()
+    assert rel_max(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("storage,bar", [("f32", 1e-5), ("f16", 1e-3)])
+def test_reference_field_reduced_precision(storage, bar):
+    """Reduced-precision storage with an averaged reference: the pressure
+    fluctuation p' = c_s^2 (rho - rho0) against the FP64 oracle, relative to
+    the initial fluctuation (rounding noise does not shrink with the damped
+    signal)."""
+    n, T = 96, 200
+    rho, ux, uy = wl.gaussian_pulses(n, n, [(48, 48)], [1e-3], [6.0], u0=(0.05, 0.0))
+    chi = wl.sponge_2d(wl.quadratic_ramp_1d(n, 16, 0.2), wl.quadratic_ramp_1d(n, 16, 0.2))
+    q = (np.ones((n, n)), np.full((n, n), 0.05), np.zeros((n, n)))
+    f0 = oracle.feq_field(rho, ux, uy)
+    ref, _ = oracle.step_avg(f0, conserved(q), T, alpha=0.01, chi=chi, variant="II")
+    lat = lbm.Lattice(n, n, rho=rho, ux=ux, uy=uy, storage=storage, variant="II", ux_base=0.05,
+                      f16_scale=1e-3)
+    lat.set_sponge(chi, (1.0, 0.05, 0.0))
+    lat.set_qref_field(*q)
+    lat.set_qref_average(0.01)
+    lat.step(T)
+    got = lat.populations()
+    lat.close()
+    rg = got.sum(axis=0) - 1.0
+    rr = ref.sum(axis=0) - 1.0
+    r0 = f0.sum(axis=0) - 1.0
+    e = math.sqrt(((rg - rr) ** 2).sum() / (r0 ** 2).sum())
+    say("  %s p' error / initial %.3e" % (storage, e))
+    assert e <= bar
+
+
+def test_uniform_field_equals_uniform_reference_bitwise():
+    """A field equal everywhere to the uniform q_ref (fixed, alpha = 0) gives
+    the same bits as the uniform reference in the one-cell kernel; clearing
+    the field returns to the uniform path."""
+    nx, ny = 90, 33
+    rho, ux, uy, chi, _ = case(nx, ny, 31)
+    qu = (1.0003, 0.041, -0.002)
+    outs = []
+    for mode in ("uniform", "field", "cleared"):
+        lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage="f32", variant="II", ux_base=0.04)
+        lat.set_tuning(kernel=0, block=256)
+        lat.set_sponge(chi, qu)
+        if mode != "uniform":
+            lat.set_qref_field(np.full((ny, nx), qu[0]), np.full((ny, nx), qu[1]),
+                               np.full((ny, nx), qu[2]))
+        if mode == "cleared":
+            lat.step(3)
+            lat.set_qref_field(None, None, None)
+        lat.step(20 if mode != "cleared" else 17)
+        outs.append(lat.save_state())
+        lat.close()
+    np.testing.assert_array_equal(outs[1], outs[0])
+    np.testing.assert_array_equal(outs[2], outs[0])
+
+
+def test_reference_field_round_trip_and_batch_refusal():
+    nx, ny = 40, 30
+    rho, ux, uy, chi, q = case(nx, ny, 41)
+    lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage="f64", variant="II", ux_base=0.04)
+    lat.set_qref_field(*q)
+    for a, b in zip(lat.qref_field(), q):
+        np.testing.assert_allclose(a, b, rtol=1e-15, atol=1e-15)
+    with pytest.raises(lbm.LbmError):
+        lbm.Batch([lat])
+    with pytest.raises(lbm.LbmError):
+        lat.set_qref_average(1.5)
+    lat.set_qref_field(None, None, None)
+    with pytest.raises(lbm.LbmError):
+        lat.set_qref_average(0.1)
+    lat.close()
