@@ -38,14 +38,18 @@ PEAK_VALU_TFLOPS = 78.6
 FLOPS_PER_UPDATE = {"none": 139, "I": 180, "II": 180, "III": 171, "visc": 152}
 METRIC = "D2Q9 MRT+sponge MLUPS & %HBM peak; batched-served vs plain MLUPS, p99 latency"
 CSRC = os.path.join(ROOT, "paper_1203_6350_amd", "csrc")
-KERNEL_SOURCES = [os.path.join(CSRC, f) for f in
-                  ("lbm_kernels.hip", "lbm_strip.h", "lbm_launch.h", "lbm_device.h")]
+# sources of the two step-kernel families: the K-step strip kernel and the
+# one-step kernels
+KERNEL_SOURCES = {
+    "strip": [os.path.join(CSRC, f) for f in ("lbm_strip.h", "lbm_launch.h", "lbm_device.h")],
+    "one_step": [os.path.join(CSRC, f) for f in ("lbm_kernels.hip", "lbm_launch.h", "lbm_device.h")],
+}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_f32_typeII_4096_pmc.txt")
 
 
-def kernel_hash():
+def kernel_hash(family):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES[family]:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -58,10 +62,11 @@ def counter_traffic(tuning):
     if not os.path.exists(PMC_SUMMARY):
         return None
     txt = open(PMC_SUMMARY).read()
-    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    family = "strip" if tuning["kernel"] >= 2 else "one_step"
+    m = re.search(r"%s_kernel_sources_sha256_16:\s*(\w+)" % family, txt)
     key = "%d,%d,%d" % (tuning["kernel"], tuning["block"], tuning.get("rows", 0) if tuning["kernel"] >= 2 else 0)
     b = re.search(r"scaled_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_hash():
+    if not m or not b or m.group(1) != kernel_hash(family):
         return None
     return float(b.group(1))
 
@@ -376,6 +381,40 @@ def cpu_baseline(spec, fields, steps, wl=None):
     return out
 
 
+def qref_leg(lbm, wl, torch, n=4096, steps=400, warmup=20, alpha=1e-3):
+    """The headline workload with a per-cell reference state that follows the
+    flow as a running mean (rate alpha): one-step kernel, the field read and
+    written every step (FP32: 72 + 24 B per cell update)."""
+    sp = wl.large_c2(variant="II", storage="f32", n=n)
+    rho, ux, uy = sp.fields()
+    stream = torch.cuda.current_stream()
+    lat = lbm.Lattice(sp.nx, sp.ny, rho=rho, ux=ux, uy=uy, storage="f32", variant="II", s=sp.s,
+                      ux_base=sp.base_state[1], stream=stream)
+    cx, cy = sp.chi_1d()
+    lat.set_sponge_separable(cx, cy, "max", sp.qref)
+    lat.set_qref_field(rho, ux, uy)
+    out = {}
+    for a in (0.0, alpha):
+        lat.set_qref_average(a)
+        lat.step(warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        b = 72 + (24 if a else 12)
+        out["alpha=%g" % a] = {"mlups": sp.nx * sp.ny / ms / 1e3, "ms_per_step": ms,
+                               "bytes_per_cell": b,
+                               "hbm_gbps": b * sp.nx * sp.ny / (ms * 1e-3) / 1e9,
+                               "hbm_frac": b * sp.nx * sp.ny / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS}
+    d = lat.diagnostics()
+    lat.close()
+    out["nonfinite_cells"] = float(d[6])
+    return out
+
+
 def storages_leg(lbm, wl, torch, n, steps, warmup):
     """The headline workload in FP64 and FP16 storage (autotuned launch shape)."""
     out = {}
@@ -404,6 +443,7 @@ def main():
     ap.add_argument("--variants", default="II,I,III")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-storages", action="store_true")
+    ap.add_argument("--no-qref", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -504,6 +544,9 @@ def main():
     if not args.no_storages and args.storage == "f32":
         print("bench: FP64 and FP16 storage", file=sys.stderr, flush=True)
         out["storages"] = storages_leg(lbm, wl, torch, args.n, 400, 20)
+    if not args.no_qref and args.storage == "f32":
+        print("bench: time-averaged reference state", file=sys.stderr, flush=True)
+        out["qref_average"] = qref_leg(lbm, wl, torch, n=args.n)
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)
