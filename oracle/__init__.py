@@ -70,6 +70,10 @@ def lib():
                                       ctypes.c_double, ctypes.c_int, ctypes.c_double, i64,
                                       ctypes.c_int]
         L.oracle_step_avg.restype = ctypes.c_int
+        L.oracle_step_line_source.argtypes = [i64, i64, dp, dp, dp, dp, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int, dp, ctypes.c_int,
+                                              i64, i64, ctypes.c_int]
+        L.oracle_step_line_source.restype = ctypes.c_int
         L.oracle_collide.argtypes = [i64, dp, dp, dp, dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, dp]
         L.oracle_collide.restype = ctypes.c_int
@@ -169,6 +173,29 @@ def step_avg(f, cf, nsteps, *, alpha, s=S_MRT_DEFAULT, chi=None, n=0.5, m=0.5, v
     if rc != 0:
         raise ValueError("oracle_step_avg rejected its arguments")
     return f, cf
+
+
+def step_line_source(f, nsteps, *, source, outflow=True, t0=0, s=S_MRT_DEFAULT, chi=None,
+                     qref=(1.0, 0.0, 0.0), n=0.5, m=0.5, variant="II", nthreads=0):
+    """Advance ``f[9][ny][nx]`` by ``nsteps`` steps on the line-source channel
+    of Sec. 4.2: after each collision the column x = 0 becomes
+    f^eq(rho_src(t + 1), u_src) with rho_src(t) = rho0 + amp sin(2 pi freq t +
+    phase), and (outflow) the column x = nx - 1 a copy of column nx - 2.
+
+    ``source`` = (rho0, amp, freq, phase, ux, uy); ``t0`` = step index of
+    the input state. Returns a new array.
+    """
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    assert f.ndim == 3 and f.shape[0] == 9
+    ny, nx = f.shape[1:]
+    chi_a = None if chi is None else _f64(np.broadcast_to(chi, (ny, nx)))
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    rc = lib().oracle_step_line_source(nx, ny, _dp(f), _dp(chi_a), _dp(_f64(qref)), _dp(_f64(s)),
+                                       float(n), float(m), v, _dp(_f64(source)), int(bool(outflow)),
+                                       int(t0), int(nsteps), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_step_line_source rejected its arguments")
+    return f
 
 
 def collide(fin, *, s=S_MRT_DEFAULT, chi=0.0, qref=(1.0, 0.0, 0.0), n=0.5,

@@ -331,6 +331,69 @@ int oracle_step_avg(int64_t nx, int64_t ny, double *f, const double *chi, double
   return 0;
 }
 
+/*
+ * oracle_step_line_source -- like oracle_step (uniform q_ref) on a channel
+ * with the acoustic line source of Sec. 4.2: after each step's collision
+ * the column x = 0 is replaced by the source's equilibrium
+ * f^eq(rho_src(t + 1), u_src), rho_src(t) = rho0 + amp sin(2 pi freq t + phase)
+ * (t counted in steps, t0 the step index of the input state), and, if
+ * outflow != 0, the column x = nx - 1 by a copy of column nx - 2
+ * (zero-gradient outflow); streaming then proceeds as on the periodic
+ * lattice, which these two columns' overrides cut in x.
+ *   src: {rho0, amp, freq, phase, ux, uy}.
+ */
+int oracle_step_line_source(int64_t nx, int64_t ny, double *f, const double *chi,
+                            const double *qref_uniform, const double *s, double n, double m,
+                            int variant, const double *src, int outflow, int64_t t0,
+                            int64_t nsteps, int nthreads) {
+  setup();
+  if (nx < 3 || ny < 1 || !f || !s || !qref_uniform || !src || nsteps < 0) return -1;
+  const int64_t N = nx * ny;
+  double *post = (double *)malloc(sizeof(double) * Q * N);
+  if (!post) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  const double PI = 3.14159265358979323846;
+  for (int64_t t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < ny; ++y) {
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t c = y * nx + x;
+        double fin[Q], fo[Q];
+        for (int i = 0; i < Q; ++i) fin[i] = f[i * N + c];
+        collide_cell(fin, chi ? chi[c] : 0.0, qref_uniform[0], qref_uniform[1], qref_uniform[2],
+                     s, n, m, variant, fo);
+        for (int i = 0; i < Q; ++i) post[i * N + c] = fo[i];
+      }
+    }
+    /* boundary columns */
+    const double tn = (double)(t0 + t + 1);
+    const double rs = src[0] + src[1] * sin(2.0 * PI * src[2] * tn + src[3]);
+    double fs[Q];
+    feq(rs, rs * src[4], rs * src[5], fs);
+    for (int64_t y = 0; y < ny; ++y) {
+      for (int i = 0; i < Q; ++i) {
+        post[i * N + y * nx] = fs[i];
+        if (outflow) post[i * N + y * nx + nx - 1] = post[i * N + y * nx + nx - 2];
+      }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < ny; ++y) {
+      for (int64_t x = 0; x < nx; ++x) {
+        for (int i = 0; i < Q; ++i) {
+          const int64_t xs = wrap(x - CX[i], nx), ys = wrap(y - CY[i], ny);
+          f[i * N + y * nx + x] = post[i * N + ys * nx + xs];
+        }
+      }
+    }
+  }
+  free(post);
+  return 0;
+}
+
 /* One collision (no streaming) for a batch of independent cells, used by the
  * Von Neumann cross-checks.  fin, fout: [ncell][9]. */
 int oracle_collide(int64_t ncell, const double *fin, const double *chi,

@@ -40,6 +40,10 @@ MUTANTS = {
     "mean_rate_complement": ("cf[c] = rf + alpha * (mom[0] - rf);", "cf[c] = rf + (1.0 - alpha) * (mom[0] - rf);"),
     "mean_momentum_component": ("cf[2 * N + c] = jyf + alpha * (mom[2] - jyf);", "cf[2 * N + c] = jyf + alpha * (mom[1] - jyf);"),
     "mean_velocity_not_momentum": ("rf, jxf / rf, jyf / rf, s, n, m, variant, fo);", "rf, jxf, jyf, s, n, m, variant, fo);"),
+    "source_time_offset": ("const double tn = (double)(t0 + t + 1);", "const double tn = (double)(t0 + t);"),
+    "source_velocity_dropped": ("feq(rs, rs * src[4], rs * src[5], fs);", "feq(rs, 0.0, 0.0, fs);"),
+    "source_sine_sign": ("src[0] + src[1] * sin(", "src[0] - src[1] * sin("),
+    "outflow_wrong_column": ("post[i * N + y * nx + nx - 1] = post[i * N + y * nx + nx - 2];", "post[i * N + y * nx + nx - 1] = post[i * N + y * nx + nx - 3];"),
 }
 
 

@@ -533,3 +533,88 @@ def test_averaged_reference_equilibrium_is_fixed_point():
                                 else chi, variant=var)
         np.testing.assert_allclose(a, f0, rtol=0, atol=1e-15)
         np.testing.assert_allclose(cf, cf0, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------ line source and outflow (Sec. 4.2)
+
+SRC = (1.0, 1e-4, 0.01, 0.3, 0.04, 0.0)   # rho0, amp, freq (per step), phase, ux, uy
+
+
+def _rho_src(t, src=SRC):
+    return src[0] + src[1] * np.sin(2 * np.pi * src[2] * t + src[3])
+
+
+def test_line_source_injects_the_source_equilibrium():
+    """After a step from time t0, the populations moving in +x at x = 1 are
+    those of the source equilibrium f^eq(rho_src(t0 + 1), u_src) (closed form,
+    any state, any sponge, any variant)."""
+    f = random_state(12, 7, 61, u0=(0.04, 0.0))
+    chi = np.random.default_rng(62).uniform(0, 0.3, (7, 12))
+    for var, t0 in (("II", 0), ("III", 17), ("none", 5)):
+        out = oracle.step_line_source(f, 1, source=SRC, t0=t0, chi=chi, variant=var,
+                                      qref=(1.0, 0.04, 0.0))
+        rs = _rho_src(t0 + 1)
+        feq = oracle.feq_field(np.full((7, 1), rs), np.full((7, 1), SRC[4]),
+                               np.full((7, 1), SRC[5]))
+        for i in (1, 5, 8):
+            np.testing.assert_allclose(out[i, :, 1], feq[i, :, 0], rtol=0, atol=1e-16)
+
+
+def test_line_source_outflow_copies_the_last_interior_column():
+    """With outflow, the populations moving in -x at x = nx - 2 after a step
+    are the post-collision populations of column nx - 2 itself (pulled from
+    column nx - 1, which holds its copy)."""
+    nx, ny = 10, 6
+    f = random_state(nx, ny, 63, u0=(0.04, 0.0))
+    M, _, cx, cy, _ = oracle.tables()
+    out = oracle.step_line_source(f, 1, source=SRC, variant="II", qref=(1.0, 0.04, 0.0))
+    post = oracle.collide(f[:, :, nx - 2].T, variant="II", qref=(1.0, 0.04, 0.0)).T  # [9][ny]
+    for i in (3, 6, 7):
+        np.testing.assert_allclose(out[i, :, nx - 2], np.roll(post[i], int(cy[i])), rtol=0,
+                                   atol=1e-16)
+
+
+def test_line_source_outflow_is_local():
+    """The outflow column influences the channel at most one cell per step:
+    a channel twice as long gives the same populations on x < nx - 1 - T."""
+    nx, ny, T = 40, 5, 15
+    f = random_state(2 * nx, ny, 64, u0=(0.04, 0.0))
+    short = oracle.step_line_source(f[:, :, :nx], T, source=SRC, variant="II",
+                                    qref=(1.0, 0.04, 0.0))
+    long_ = oracle.step_line_source(f, T, source=SRC, variant="II", qref=(1.0, 0.04, 0.0))
+    np.testing.assert_array_equal(short[:, :, 1:nx - 1 - T], long_[:, :, 1:nx - 1 - T])
+
+
+def test_line_source_y_invariance():
+    """A y-uniform state with the y-uniform source keeps every row equal to
+    the one-row channel."""
+    nx = 30
+    row = random_state(nx, 1, 65, u0=(0.04, 0.0))
+    f = np.repeat(row, 6, axis=1)
+    a = oracle.step_line_source(f, 40, source=SRC, variant="II", qref=(1.0, 0.04, 0.0),
+                                chi=np.tile(np.linspace(0, 0.3, nx), (6, 1)))
+    b = oracle.step_line_source(row, 40, source=SRC, variant="II", qref=(1.0, 0.04, 0.0),
+                                chi=np.linspace(0, 0.3, nx)[None, :])
+    for y in range(6):
+        np.testing.assert_array_equal(a[:, y], b[:, 0])
+
+
+@pytest.mark.parametrize("u0", [0.0, 0.1])
+def test_line_source_emits_the_acoustic_wavelength(u0):
+    """The source emits a plane wave of wavelength (c_s + u0) / freq: the mean
+    spacing of the downward zero crossings of rho' behind the front matches
+    it within 2% (freq = 0.01 per step, as in the paper's set-up)."""
+    nx, T = 600, 420
+    src = (1.0, 1e-4, 0.01, 0.0, u0, 0.0)
+    rho = np.ones((1, nx))
+    f0 = oracle.feq_field(rho, np.full((1, nx), u0), np.zeros((1, nx)))
+    S = (0.0, 0.0, 0.0) + (1.9988,) * 6
+    f = oracle.step_line_source(f0, T, source=src, s=S, variant="none", qref=(1.0, u0, 0.0))
+    rp = f.sum(axis=0)[0] - 1.0
+    cs = 1 / np.sqrt(3)
+    front = int((cs + u0) * T)
+    seg = rp[5:front - 40]
+    down = np.where((seg[:-1] > 0) & (seg[1:] <= 0))[0]
+    x0 = down + seg[down] / (seg[down] - seg[down + 1])   # linear interpolation
+    lam = np.diff(x0).mean()
+    assert abs(lam / ((cs + u0) / 0.01) - 1) < 0.02, lam
