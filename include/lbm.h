@@ -215,6 +215,21 @@ int lbm_set_qref_field(lbm_handle *h, const double *rho_f, const double *ux_f,
 int lbm_set_qref_average(lbm_handle *h, double alpha);
 int lbm_get_qref_field(lbm_handle *h, double *rho_f, double *ux_f, double *uy_f);
 
+/* ---- acoustic line source with outflow (Sec. 4.2) ---------------------
+ * Turns the lattice into a channel in x: after each step's collision the
+ * column x = 0 holds the source's equilibrium f^eq(rho_src(t), u_src),
+ * rho_src(t) = rho0 + amp sin(2 pi freq t + phase), t = the step index the
+ * step ends at (the handle's step count), freq in cycles per step; with
+ * outflow = 1 the column x = nx - 1 holds a copy of column nx - 2 after the
+ * collision (zero-gradient outflow). y stays periodic. Needs nx >= 3 and
+ * rho0 - |amp| > 0; src = NULL (with outflow = 0) makes x periodic again.
+ * While set, lbm_step runs the one-cell-per-thread kernel whatever the
+ * tuning, and the handle cannot join a batch or take a reference field. */
+typedef struct lbm_line_source {
+  double rho0, amp, freq, phase, ux, uy;
+} lbm_line_source;
+int lbm_set_line_source(lbm_handle *h, const lbm_line_source *src, int32_t outflow);
+
 /* ---- kernel tuning ----------------------------------------------------
  * Launch shape of the step kernel. Every choice computes the same per-cell
  * arithmetic, so results are bit-identical across tunings. */

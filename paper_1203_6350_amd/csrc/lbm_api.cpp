@@ -76,6 +76,9 @@ struct lbm_handle {
   void *qf = nullptr;         // compute type [3][qps]: per-cell reference, or NULL
   int64_t qps = 0;
   double qalpha = 0.0;        // running-mean rate of the reference
+  int channel = 0;            // line source at x = 0 (Sec. 4.2)
+  int outflow = 0;            // zero-gradient outflow at x = nx - 1
+  lbm_line_source src = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double *diag_partials = nullptr;
   double *diag_out = nullptr;
   int64_t steps = 0;
@@ -140,6 +143,38 @@ void fill_cfg(lbm_handle *h) {
   s.qfield = h->qf;
   s.qps = h->qps;
   s.qalpha = h->qf ? h->qalpha : 0.0;
+  s.channel = h->channel;
+  s.outflow = h->outflow;
+}
+
+// Equilibrium deviation f^eq_i(rho_b + dr, j_b + dj) - f^eq_i(rho_b, j_b) in
+// FP64, every term O(dr, dj): the same expression the device's
+// initialisation evaluates.
+void feq_dev_host(double dr, double djx, double djy, double rho_b, double ubx, double uby,
+                  double out[9]) {
+  const double rho = rho_b + dr;
+  for (int i = 0; i < 9; ++i) {
+    const double cx = lbm::cx_of(i), cy = lbm::cy_of(i);
+    const double dJ = cx * djx + cy * djy;
+    const double Ub = cx * ubx + cy * uby;
+    const double vJ = dJ - Ub * dr;
+    const double dq_c = 2.0 * Ub * dJ - Ub * Ub * dr + vJ * vJ / rho;
+    const double vx = djx - ubx * dr, vy = djy - uby * dr;
+    const double dq_x = 2.0 * ubx * djx - ubx * ubx * dr + vx * vx / rho;
+    const double dq_y = 2.0 * uby * djy - uby * uby * dr + vy * vy / rho;
+    out[i] = lbm::w_of(i) * (dr + 3.0 * dJ + 4.5 * dq_c - 1.5 * (dq_x + dq_y));
+  }
+}
+
+// Source deviations stored at x = 0 by the step that ends at step index t.
+void source_dev(const lbm_handle *h, int64_t t, double out[9]) {
+  const double PI = 3.14159265358979323846;
+  const lbm_line_source &q = h->src;
+  const double rs = q.rho0 + q.amp * std::sin(2.0 * PI * q.freq * (double)t + q.phase);
+  const double rb = h->user.rho_base, ubx = h->user.ux_base, uby = h->user.uy_base;
+  const double dr = rs - rb;
+  feq_dev_host(dr, dr * q.ux + rb * (q.ux - ubx), dr * q.uy + rb * (q.uy - uby), rb, ubx, uby,
+               out);
 }
 
 // Upload an FP64 host array converted to the compute type of the handle.
@@ -377,8 +412,8 @@ int lbm_step(lbm_handle *h, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   int64_t k = 0;
   const int per = h->cfg.kernel;  // time steps per launch of the multi-step kernel
-  // a per-cell reference state runs in the one-step kernel only
-  if (per >= lbm::KERNEL_MULTI_MIN && !h->qf) {
+  // a per-cell reference state or a channel runs in the one-step kernel only
+  if (per >= lbm::KERNEL_MULTI_MIN && !h->qf && !h->channel) {
     while (n - k >= 2) {
       const int m = n - k >= per ? per : (int)(n - k);
       hipError_t e = lbm::launch_multi_steps(h->cfg, m, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
@@ -389,6 +424,7 @@ int lbm_step(lbm_handle *h, int64_t n) {
     }
   }
   for (; k < n; ++k) {
+    if (h->channel) source_dev(h, h->steps + 1, h->cfg.src_dev);
     hipError_t e = lbm::launch_step(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel");
     h->cur = 1 - h->cur;
@@ -633,6 +669,7 @@ int lbm_set_qref_field(lbm_handle *h, const double *rho_f, const double *ux_f,
     return LBM_OK;
   }
   if (!rho_f || !ux_f || !uy_f) return fail(LBM_EINVAL, "give all three reference fields or none");
+  if (h->channel) return fail(LBM_ESTATE, "a reference field cannot be combined with a line source");
   const int64_t nx = h->user.nx, ny = h->user.ny, pitch = h->cfg.pitch;
   for (int64_t c = 0; c < nx * ny; ++c)
     if (!(rho_f[c] > 0) || !is_fin(rho_f[c]) || !is_fin(ux_f[c]) || !is_fin(uy_f[c]))
@@ -687,6 +724,29 @@ int lbm_get_qref_field(lbm_handle *h, double *rho_f, double *ux_f, double *uy_f)
       ux_f[c] = (rb * ubx + host[(size_t)(qps + d)]) / rho;
       uy_f[c] = (rb * uby + host[(size_t)(2 * qps + d)]) / rho;
     }
+  return LBM_OK;
+}
+
+int lbm_set_line_source(lbm_handle *h, const lbm_line_source *src, int32_t outflow) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!src) {
+    if (outflow) return fail(LBM_EINVAL, "an outflow boundary needs the line source");
+    h->channel = h->outflow = 0;
+    fill_cfg(h);
+    return LBM_OK;
+  }
+  if (h->qf) return fail(LBM_ESTATE, "a line source cannot be combined with a reference field");
+  if (h->user.nx < 3) return fail(LBM_EINVAL, "a channel needs nx >= 3");
+  if (outflow != 0 && outflow != 1) return fail(LBM_EINVAL, "outflow must be 0 or 1");
+  const double *v = &src->rho0;
+  for (int i = 0; i < 6; ++i)
+    if (!is_fin(v[i])) return fail(LBM_EINVAL, "line source parameters must be finite");
+  if (!(src->rho0 - std::fabs(src->amp) > 0)) return fail(LBM_EINVAL, "source density must stay > 0");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->src = *src;
+  h->channel = 1;
+  h->outflow = outflow;
+  fill_cfg(h);
   return LBM_OK;
 }
 
@@ -848,6 +908,8 @@ int validate_members(lbm_handle *const *members, int32_t count) {
       if (members[j] == members[i]) return fail(LBM_EINVAL, "members must be distinct");
     if (members[i]->qf)
       return fail(LBM_EINVAL, "members with a per-cell reference state are not batched");
+    if (members[i]->channel)
+      return fail(LBM_EINVAL, "members with a line source are not batched");
   }
   return LBM_OK;
 }

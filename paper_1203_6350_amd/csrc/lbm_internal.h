@@ -34,6 +34,10 @@ struct StepConfig {
   void *qfield;
   int64_t qps;
   double qalpha;         // running-mean rate of the reference (0: fixed)
+  // channel in x (line source at x = 0, optional outflow at x = nx - 1)
+  int channel;           // 0: periodic in x
+  int outflow;
+  double src_dev[9];     // post-collision deviations stored at x = 0 this step
 };
 
 enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MAX = 4 };

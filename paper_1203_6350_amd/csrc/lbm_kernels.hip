@@ -227,6 +227,73 @@ __global__ __launch_bounds__(256) void step_qfield(
   }
 }
 
+// One step on a channel (the acoustic line source of Sec. 4.2): the column
+// x = 0 stores the source's equilibrium (deviations given per step in sdev)
+// in place of its collision result; with outflow, the column x = nx - 1
+// stores the update of column nx - 2 (zero-gradient outflow), which its
+// thread computes again from the same inputs. All other cells step as on the
+// periodic lattice; the two overridden columns cut it in x.
+template <typename S>
+struct SrcDev {
+  typename Store<S>::C v[9];
+};
+
+template <typename S, int VAR, int CHI>
+__global__ __launch_bounds__(256) void step_channel(
+    const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
+    CollideParams<typename Store<S>::C> p,
+    const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix,
+    const typename Store<S>::C *__restrict__ chiy, SrcDev<S> sdev, int outflow) {
+  typedef typename Store<S>::C C;
+  const int bpr = (L.nx + 255) / 256;
+  const int y = blockIdx.x / bpr;
+  const int xo = (blockIdx.x - y * bpr) * 256 + threadIdx.x;  // column written
+  if (xo >= L.nx) return;
+  const int64_t r0 = (int64_t)y * L.pitch;
+  const int64_t ps = L.ps;
+  if (xo == 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Store<S>::store(dst + i * ps + r0, sdev.v[i], L.inv_scale[i]);
+    return;
+  }
+  const int x = outflow && xo == L.nx - 1 ? L.nx - 2 : xo;  // column updated
+  const int xm = x == 0 ? L.nx - 1 : x - 1;
+  const int xp = x == L.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? L.ny - 1 : y - 1;
+  const int yp = y == L.ny - 1 ? 0 : y + 1;
+  const int64_t rm = (int64_t)ym * L.pitch, rp = (int64_t)yp * L.pitch;
+  C g[9];
+  g[0] = Store<S>::load(src + 0 * ps + r0 + x, L.scale[0]);
+  g[1] = Store<S>::load(src + 1 * ps + r0 + xm, L.scale[1]);
+  g[2] = Store<S>::load(src + 2 * ps + rm + x, L.scale[2]);
+  g[3] = Store<S>::load(src + 3 * ps + r0 + xp, L.scale[3]);
+  g[4] = Store<S>::load(src + 4 * ps + rp + x, L.scale[4]);
+  g[5] = Store<S>::load(src + 5 * ps + rm + xm, L.scale[5]);
+  g[6] = Store<S>::load(src + 6 * ps + rm + xp, L.scale[6]);
+  g[7] = Store<S>::load(src + 7 * ps + rp + xp, L.scale[7]);
+  g[8] = Store<S>::load(src + 8 * ps + rp + xm, L.scale[8]);
+  const C chi = chi_at<C, CHI>(chi_field, chix, chiy, r0 + x, x, y);
+  collide<C, VAR>(g, chi, p);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Store<S>::store(dst + i * ps + r0 + xo, g[i], L.inv_scale[i]);
+}
+
+template <typename S, int VAR, int CHI>
+static hipError_t launch_channel(const StepConfig &c, const void *src, void *dst,
+                                 hipStream_t stream) {
+  typedef typename Store<S>::C C;
+  Lat<S> L = make_lat<S>(c);
+  CollideParams<C> p = make_params<C>(c);
+  SrcDev<S> sd;
+  for (int i = 0; i < 9; ++i) sd.v[i] = C(c.src_dev[i]);
+  const int64_t blocks = (int64_t)((c.nx + 255) / 256) * c.ny;
+  step_channel<S, VAR, CHI><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(
+      (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
+      (const C *)c.chi_y, sd, c.outflow);
+  return hipGetLastError();
+}
+
 template <typename S, int VAR, int CHI>
 static hipError_t launch_qfield(const StepConfig &c, const void *src, void *dst,
                                 hipStream_t stream) {
@@ -278,6 +345,7 @@ template <typename S, int VAR, int CHI>
 static hipError_t launch_step_t(const StepConfig &c, const void *src,
                                 void *dst, hipStream_t stream) {
   if (c.qfield) return launch_qfield<S, VAR, CHI>(c, src, dst, stream);
+  if (c.channel) return launch_channel<S, VAR, CHI>(c, src, dst, stream);
   const int kernel = c.kernel == KERNEL_VEC && vec_supported(c) ? KERNEL_VEC : KERNEL_GENERIC;
   if (kernel == KERNEL_GENERIC) {
     switch (c.block) {

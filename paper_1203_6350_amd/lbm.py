@@ -49,6 +49,11 @@ class lbm_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t)]
 
 
+class lbm_line_source(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("amp", ctypes.c_double), ("freq", ctypes.c_double),
+                ("phase", ctypes.c_double), ("ux", ctypes.c_double), ("uy", ctypes.c_double)]
+
+
 class lbm_tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("rows", ctypes.c_int32)]
@@ -103,6 +108,7 @@ def load(path: str | None = None):
         "lbm_get_info": [_H, ctypes.POINTER(lbm_info)],
         "lbm_set_tuning": [_H, ctypes.POINTER(lbm_tuning)],
         "lbm_set_qref_field": [_H, _DP, _DP, _DP],
+        "lbm_set_line_source": [_H, ctypes.POINTER(lbm_line_source), i32],
         "lbm_set_qref_average": [_H, ctypes.c_double],
         "lbm_get_qref_field": [_H, _DP, _DP, _DP],
         "lbm_get_tuning": [_H, ctypes.POINTER(lbm_tuning)],
@@ -260,6 +266,15 @@ def lbm_set_qref_field(h, rho_f=None, ux_f=None, uy_f=None):
     _u, pu = _host(ux_f, n)
     _v, pv = _host(uy_f, n)
     _check(load().lbm_set_qref_field(h, pr, pu, pv))
+
+
+def lbm_set_line_source(h, source=None, outflow=True):
+    """source = (rho0, amp, freq, phase, ux, uy) or None (periodic x again)."""
+    if source is None:
+        _check(load().lbm_set_line_source(h, None, 0))
+        return
+    src = lbm_line_source(*(float(v) for v in source))
+    _check(load().lbm_set_line_source(h, ctypes.byref(src), int(bool(outflow))))
 
 
 def lbm_set_qref_average(h, alpha):
@@ -431,6 +446,9 @@ class Lattice:
 
     def set_qref_average(self, alpha):
         lbm_set_qref_average(self.h, alpha)
+
+    def set_line_source(self, source=None, outflow=True):
+        lbm_set_line_source(self.h, source, outflow)
 
     def qref_field(self):
         return lbm_get_qref_field(self.h)
