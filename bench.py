@@ -23,6 +23,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -415,6 +417,56 @@ def qref_leg(lbm, wl, torch, n=4096, steps=400, warmup=20, alpha=1e-3):
     return out
 
 
+def _line_source_run(lbm, wl, cfg):
+    nx, ny = cfg["nx"], cfg["ny"]
+    u0 = cfg["u0"]
+    lat = lbm.Lattice(nx, ny, rho=np.ones((ny, nx)), ux=np.full((ny, nx), u0),
+                      uy=np.zeros((ny, nx)), storage="f64", variant=cfg["variant"], s=cfg["s"],
+                      ux_base=u0)
+    lat.set_sponge_separable(cfg["profile"], None, "max", (1.0, u0, 0.0))
+    lat.set_line_source(cfg["source"], True)
+    t0 = time.perf_counter()
+    lat.step(cfg["t_sample"])
+    rho, _, _ = lat.moments()
+    dt = time.perf_counter() - t0
+    lat.close()
+    return rho - 1.0, dt
+
+
+def line_source_leg(lbm, wl):
+    """Section 4.2: the acoustic line source through an absorbing layer at the
+    outflow, sampled at T_o + 10 T_p. rho' along the channel against a
+    reference channel three times longer without a layer (no reflection can
+    reach its first part by then): relative L2 error over the physical region,
+    per strategy, with and without mean flow, and the layer thickness that
+    Type II needs."""
+    out = {}
+    for u0 in (0.0, 0.1):
+        ref_cfg = wl.paper_line_source("none", thickness=0.0, u0=u0, length_factor=3)
+        ref, _ = _line_source_run(lbm, wl, ref_cfg)
+        for strat in ("none", "visc", "II"):
+            cfg = wl.paper_line_source(strat, u0=u0)
+            rp, dt = _line_source_run(lbm, wl, cfg)
+            phys = slice(1, cfg["nx"] - cfg["layer_cells"])
+            a, b = rp[0, phys], ref[0, phys]
+            out["u0=%g,%s" % (u0, strat)] = {
+                "rel_l2_error": float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum())),
+                "rows_identical": bool((rp == rp[:1]).all()), "steps": cfg["t_sample"],
+                "mlups": cfg["nx"] * cfg["ny"] * cfg["t_sample"] / dt / 1e6}
+    ref_cfg = wl.paper_line_source("none", thickness=0.0, length_factor=3)
+    ref, _ = _line_source_run(lbm, wl, ref_cfg)
+    thick = {}
+    for d in (0.1, 0.2, 0.3, 0.5, 0.8):
+        cfg = wl.paper_line_source("II", thickness=d)
+        rp, _ = _line_source_run(lbm, wl, cfg)
+        phys = slice(1, cfg["nx"] - int(round(0.8 * 200)))   # the same region for every d
+        a, b = rp[0, phys], ref[0, phys]
+        thick["%g" % d] = float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+    out["typeII_thickness_rel_l2"] = thick
+    out["wavelength_cells"] = wl.paper_line_source()["wavelength_cells"]
+    return out
+
+
 def storages_leg(lbm, wl, torch, n, steps, warmup):
     """The headline workload in FP64 and FP16 storage (autotuned launch shape)."""
     out = {}
@@ -444,6 +496,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-storages", action="store_true")
     ap.add_argument("--no-qref", action="store_true")
+    ap.add_argument("--no-line-source", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -547,6 +600,9 @@ def main():
     if not args.no_qref and args.storage == "f32":
         print("bench: time-averaged reference state", file=sys.stderr, flush=True)
         out["qref_average"] = qref_leg(lbm, wl, torch, n=args.n)
+    if not args.no_line_source:
+        print("bench: the paper's line source", file=sys.stderr, flush=True)
+        out["line_source"] = line_source_leg(lbm, wl)
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)

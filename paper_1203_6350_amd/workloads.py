@@ -213,6 +213,49 @@ def paper_pulse(strategy="II", thickness_b=4, u0=0.0, s=1.9999, n=200, b_cells=1
     return spec, prof, prof.copy()
 
 
+def right_ramp_depth(n: int, width: int) -> np.ndarray:
+    """xi(i) = max(0, (W - (n-1-i)) / W): 1 at the last cell, 0 from depth W
+    inwards (a layer at the right end only)."""
+    i = np.arange(n, dtype=np.float64)
+    if width <= 0:
+        return np.zeros(n)
+    return np.maximum(0.0, (width - (n - 1 - i)) / width)
+
+
+def paper_line_source(strategy="II", thickness=0.8, u0=0.0, cells_per_unit=200, length=4.0,
+                      height=1.0, amp=1e-3, omega=2.0, re=1e6, length_factor=1):
+    """The acoustic line source of Section 4.2 in lattice units: a channel of
+    length W = 4H, H = 1, with ``cells_per_unit`` cells per unit length;
+    rho_src = 1 + amp sin(2 pi omega t) at x = 0 (omega = 2, i.e. omega /
+    cells_per_unit cycles per step; wavelength c_s / omega), mean flow u0
+    along x, periodic in y, outflow at the right; Re = 1/nu = 1e6 in the
+    paper's units fixes s; chi = 4/s - 0.001 with the normalised profile of
+    eq. normalizedsigma over a layer of ``thickness`` at the right end (the
+    viscosity strategy ramps the rates to 1 over it; 'none' has no layer).
+    ``length_factor`` stretches the channel (the reference run). Returns a
+    dict with nx, ny, s, variant, profile (along x), source tuple, and the
+    paper's sample time T_o + 10 T_p in steps."""
+    nx = int(round(length * cells_per_unit * length_factor))
+    ny = int(round(height * cells_per_unit))
+    nu = cells_per_unit / re            # lattice viscosity: dt = dx = 1 / cells_per_unit
+    s = 1.0 / (nu / CS ** 2 + 0.5)
+    chi_max = 4.0 / s - 0.001
+    W = int(round(thickness * cells_per_unit))
+    xi = right_ramp_depth(nx, W)
+    if strategy == "none":
+        prof = np.zeros(nx)
+    elif strategy == "visc":
+        prof = xi
+    else:
+        prof = chi_max * np.where(xi > 0, 3125.0 * (1.0 - xi) * xi ** 4 / 256.0, 0.0)
+    freq = omega / cells_per_unit
+    t_sample = int(round(length * cells_per_unit / (CS + u0) + 10.0 / freq))
+    return {"nx": nx, "ny": ny, "s": (0.0, 0.0, 0.0) + (s,) * 6,
+            "variant": {"none": "none", "visc": "visc"}.get(strategy, strategy),
+            "profile": prof, "layer_cells": W, "source": (1.0, amp, freq, 0.0, u0, 0.0),
+            "u0": u0, "t_sample": t_sample, "wavelength_cells": CS / freq}
+
+
 def batch_c4(count=256, seed_index=3, max_exp=1.0):
     """Uneven domains N = round(64 * 8^U), U ~ U[0, max_exp]; chi_max U[0.01, 0.5];
     W U{8..64} clamped to N/4; Mach U[0, 0.3]; variant U{I, II, III};

@@ -101,3 +101,25 @@ def test_channel_checks_and_reset():
     b = lbm.Batch([lat])                  # periodic again: batchable
     b.close()
     lat.close()
+
+
+def test_paper_line_source_full_size_against_one_row_oracle():
+    """The paper's line-source channel at its size (800 x 200, Type II layer of
+    0.8, Re = 1e6, mean flow 0.1, sampled at T_m + 10 T_p = 2182 steps): every
+    GPU row is bit-identical and equals the one-row FP64 oracle (the set-up is
+    y-invariant) within 1e-12 of max |f|."""
+    cfg = wl.paper_line_source("II", u0=0.1)
+    nx, ny, T, u0 = cfg["nx"], cfg["ny"], cfg["t_sample"], cfg["u0"]
+    say("case: paper line source", nx, ny, T)
+    f0 = oracle.feq_field(np.ones((1, nx)), np.full((1, nx), u0), np.zeros((1, nx)))
+    ref = oracle.step_line_source(f0, T, source=cfg["source"], s=cfg["s"],
+                                  chi=cfg["profile"][None, :], variant="II", qref=(1.0, u0, 0.0))
+    lat = lbm.Lattice(nx, ny, rho=np.ones((ny, nx)), ux=np.full((ny, nx), u0),
+                      uy=np.zeros((ny, nx)), storage="f64", variant="II", s=cfg["s"], ux_base=u0)
+    lat.set_sponge_separable(cfg["profile"], None, "max", (1.0, u0, 0.0))
+    lat.set_line_source(cfg["source"])
+    lat.step(T)
+    f = lat.populations()
+    lat.close()
+    assert (f == f[:, :1, :]).all()
+    assert rel_max(f[:, :1, :], ref) <= 1e-12
