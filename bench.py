@@ -485,6 +485,40 @@ def storages_leg(lbm, wl, torch, n, steps, warmup):
     return out
 
 
+def d3q15_leg(lbm, wl, torch, n=256, steps=200, warmup=10):
+    """The three-dimensional D3Q15 scheme (Appendix A.2) on the n^3 box with
+    mean flow, 16 pulses and a six-face separable ramp, Type II, per storage:
+    one cell per thread, every stored element read and written once per step
+    (30 elements per cell update)."""
+    spec = wl.cube_d3q15(n=n)
+    F = spec["fields"]()
+    prof = spec["profile"]
+    stream = torch.cuda.current_stream()
+    out = {"workload": "D3Q15 %d^3, Type II, separable ramp 32 cells, Mach 0.17" % n}
+    for st in ("f32", "f64", "f16"):
+        lat = lbm.Lattice3(n, n, n, rho=F[0], ux=F[1], uy=F[2], uz=F[3], storage=st,
+                           variant="II", ux_base=spec["u0"], f16_scale=1e-3, stream=stream)
+        lat.set_sponge_separable(prof, prof, prof, "max", spec["qref"])
+        lat.step(warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rho = lat.moments()[0]
+        lat.close()
+        b = 30 * {"f64": 8, "f32": 4, "f16": 2}[st]
+        cells = n ** 3
+        out[st] = {"mlups": cells / ms / 1e3, "ms_per_step": ms, "bytes_per_cell": b,
+                   "hbm_gbps": b * cells / (ms * 1e-3) / 1e9,
+                   "hbm_frac": b * cells / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                   "max_abs_rho_dev": float(np.abs(rho - 1.0).max()),
+                   "finite": bool(np.isfinite(rho).all())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -497,6 +531,7 @@ def main():
     ap.add_argument("--no-storages", action="store_true")
     ap.add_argument("--no-qref", action="store_true")
     ap.add_argument("--no-line-source", action="store_true")
+    ap.add_argument("--no-d3q15", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -603,6 +638,9 @@ def main():
     if not args.no_line_source:
         print("bench: the paper's line source", file=sys.stderr, flush=True)
         out["line_source"] = line_source_leg(lbm, wl)
+    if not args.no_d3q15:
+        print("bench: D3Q15 256^3", file=sys.stderr, flush=True)
+        out["d3q15"] = d3q15_leg(lbm, wl, torch)
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip", "lbm_batch.hip",
-           "lbm_strip_f64.hip", "lbm_strip_f32.hip", "lbm_strip_f16.hip"]
+           "lbm_strip_f64.hip", "lbm_strip_f32.hip", "lbm_strip_f16.hip", "lbm3_kernels.hip"]
 
 # - no automatic FMA contraction: the kernels place their fused multiply-adds
 #   explicitly, so every launch shape gives the same bits;

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "../../include/lbm3.h"
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -1253,6 +1254,304 @@ int vn_amplification(const lbm_vn_params *p, int64_t nk, const double *kx,
   }
   (void)hipFree(d);
   return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- D3Q15 lattice
+
+struct lbm3_handle {
+  lbm3_config user;
+  lbm::Step3Config cfg;
+  lbm3_qref q;
+  hipStream_t stream = nullptr;
+  void *lat[2] = {nullptr, nullptr};
+  int cur = 0;
+  void *chi_field = nullptr, *chi_x = nullptr, *chi_y = nullptr, *chi_z = nullptr;
+  int64_t steps = 0;
+  size_t lat_bytes = 0;
+  int64_t ncell = 0;
+};
+
+namespace {
+
+int validate3(const lbm3_config *c) {
+  if (!c) return fail(LBM_EINVAL, "config is NULL");
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(LBM_EINVAL, "nx, ny and nz must be >= 1");
+  if (c->nx > (1 << 30) || c->ny > (1 << 30) || c->nz > (1 << 30) ||
+      (double)c->nx * (double)c->ny * (double)c->nz >= 2147483648.0)
+    return fail(LBM_EINVAL, "nx * ny * nz must be below 2^31");
+  if (!(c->rho_base > 0) || !is_fin(c->rho_base))
+    return fail(LBM_EINVAL, "rho_base must be finite and > 0");
+  if (!is_fin(c->ux_base) || !is_fin(c->uy_base) || !is_fin(c->uz_base))
+    return fail(LBM_EINVAL, "base velocity must be finite");
+  for (int k = 0; k < 15; ++k)
+    if (!(c->s[k] >= 0.0 && c->s[k] <= 2.0)) return fail(LBM_EINVAL, "relaxation rates must lie in [0, 2]");
+  if (!is_fin(c->shift_n) || !is_fin(c->shift_m) || c->shift_n < 0 || c->shift_m < 0)
+    return fail(LBM_EINVAL, "shift parameters must be finite and >= 0");
+  if (c->storage < LBM_STORAGE_F64 || c->storage > LBM_STORAGE_F16)
+    return fail(LBM_EINVAL, "unknown storage mode");
+  if (c->variant < LBM_VARIANT_NONE || c->variant > LBM_VARIANT_VISC)
+    return fail(LBM_EINVAL, "unknown damping variant");
+  if (c->storage == LBM_STORAGE_F16 && !(c->f16_scale > 0 && is_fin(c->f16_scale)))
+    return fail(LBM_EINVAL, "f16_scale must be finite and > 0");
+  return LBM_OK;
+}
+
+void fill_cfg3(lbm3_handle *h) {
+  lbm::Step3Config &s = h->cfg;
+  const lbm3_config &u = h->user;
+  s.nx = (int)u.nx;
+  s.ny = (int)u.ny;
+  s.nz = (int)u.nz;
+  s.storage = u.storage;
+  s.variant = u.variant;
+  for (int k = 0; k < 15; ++k) s.s[k] = u.s[k];
+  s.n = u.shift_n;
+  s.m = u.shift_m;
+  s.rho_b = u.rho_base;
+  s.ub[0] = u.ux_base;
+  s.ub[1] = u.uy_base;
+  s.ub[2] = u.uz_base;
+  s.f16_scale = u.storage == LBM_STORAGE_F16 ? u.f16_scale : 1.0;
+  const double dr = h->q.rho_f - u.rho_base;
+  s.dcf[0] = dr;
+  s.dcf[1] = dr * h->q.ux_f + u.rho_base * (h->q.ux_f - u.ux_base);
+  s.dcf[2] = dr * h->q.uy_f + u.rho_base * (h->q.uy_f - u.uy_base);
+  s.dcf[3] = dr * h->q.uz_f + u.rho_base * (h->q.uz_f - u.uz_base);
+  s.chi_field = h->chi_field;
+  s.chi_x = h->chi_x;
+  s.chi_y = h->chi_y;
+  s.chi_z = h->chi_z;
+}
+
+void free_sponge3(lbm3_handle *h) {
+  for (void **p : {&h->chi_field, &h->chi_x, &h->chi_y, &h->chi_z}) {
+    if (*p) (void)hipFreeAsync(*p, h->stream);
+    *p = nullptr;
+  }
+}
+
+// FP64 host array -> device buffer of the compute type of the handle.
+int upload3(lbm3_handle *h, const double *src, size_t n, void **dst) {
+  const bool f64 = h->user.storage == LBM_STORAGE_F64;
+  const size_t eb = f64 ? 8 : 4;
+  HIP_TRY(hipMallocAsync(dst, n * eb, h->stream), "hipMallocAsync(sponge)");
+  std::vector<float> tmp;
+  const void *p = src;
+  if (!f64) {
+    tmp.resize(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+    p = tmp.data();
+  }
+  HIP_TRY(hipMemcpyAsync(*dst, p, n * eb, hipMemcpyHostToDevice, h->stream), "hipMemcpy(sponge)");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int check_q3(const lbm3_qref *q) {
+  if (!q) return LBM_OK;
+  if (!(q->rho_f > 0) || !is_fin(q->rho_f) || !is_fin(q->ux_f) || !is_fin(q->uy_f) ||
+      !is_fin(q->uz_f))
+    return fail(LBM_EINVAL, "q_ref must be finite with rho_f > 0");
+  return LBM_OK;
+}
+
+int check_chi3(const double *chi, size_t n, int variant) {
+  if (!chi) return LBM_OK;
+  for (size_t i = 0; i < n; ++i) {
+    if (!is_fin(chi[i]) || chi[i] < 0) return fail(LBM_EINVAL, "chi must be finite and >= 0");
+    if (variant == LBM_VARIANT_VISC && chi[i] > 1)
+      return fail(LBM_EINVAL, "the viscosity ramp coordinate must lie in [0, 1]");
+  }
+  return LBM_OK;
+}
+
+// FP64 device copy of a host array of n doubles (NULL stays NULL).
+int dev_copy3(lbm3_handle *h, const double *src, size_t n, double **dst) {
+  *dst = nullptr;
+  if (!src) return LBM_OK;
+  HIP_TRY(hipMallocAsync((void **)dst, n * 8, h->stream), "hipMallocAsync(fields)");
+  HIP_TRY(hipMemcpyAsync(*dst, src, n * 8, hipMemcpyHostToDevice, h->stream), "hipMemcpy(fields)");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm3_create(const lbm3_config *cfg, const double *rho, const double *ux, const double *uy,
+                const double *uz, lbm3_handle **out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate3(cfg);
+  if (rc) return rc;
+  rc = check_device(nullptr);
+  if (rc) return rc;
+  lbm3_handle *h = new (std::nothrow) lbm3_handle();
+  if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+  h->user = *cfg;
+  h->stream = (hipStream_t)cfg->stream;
+  h->q = lbm3_qref{cfg->rho_base, cfg->ux_base, cfg->uy_base, cfg->uz_base};
+  const int eb = lbm::elem_bytes_of(cfg->storage);
+  h->ncell = cfg->nx * cfg->ny * cfg->nz;
+  h->cfg.pitch = cfg->nx;
+  h->cfg.plane_stride = round_up(h->ncell, 256 / eb);
+  h->cfg.chi_mode = lbm::CHI_ZERO;
+  h->lat_bytes = (size_t)h->cfg.plane_stride * 15 * eb;
+  fill_cfg3(h);
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipMalloc(&h->lat[k], h->lat_bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(h->lat[k], 0, h->lat_bytes, h->stream);
+    if (e != hipSuccess) {
+      lbm3_destroy(h);
+      return hip_fail(e, "lattice allocation");
+    }
+  }
+  double *d[4];
+  const double *src[4] = {rho, ux, uy, uz};
+  for (int k = 0; k < 4; ++k) {
+    rc = dev_copy3(h, src[k], (size_t)h->ncell, &d[k]);
+    if (rc) {
+      for (int j = 0; j < k; ++j)
+        if (d[j]) (void)hipFreeAsync(d[j], h->stream);
+      lbm3_destroy(h);
+      return rc;
+    }
+  }
+  hipError_t e = lbm::launch_init3(h->cfg, d[0], d[1], d[2], d[3], h->lat[0], h->stream);
+  for (int k = 0; k < 4; ++k)
+    if (d[k]) (void)hipFreeAsync(d[k], h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    lbm3_destroy(h);
+    return hip_fail(e, "init kernel");
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm3_set_sponge(lbm3_handle *h, const double *chi, const lbm3_qref *q) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int rc = check_q3(q);
+  if (!rc) rc = check_chi3(chi, (size_t)h->ncell, h->user.variant);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  free_sponge3(h);
+  h->cfg.chi_mode = lbm::CHI_ZERO;
+  if (chi) {
+    rc = upload3(h, chi, (size_t)h->ncell, &h->chi_field);
+    if (rc) return rc;
+    h->cfg.chi_mode = lbm::CHI_FIELD;
+  }
+  if (q) h->q = *q;
+  fill_cfg3(h);
+  return LBM_OK;
+}
+
+int lbm3_set_sponge_separable(lbm3_handle *h, const double *chi_x, const double *chi_y,
+                              const double *chi_z, int32_t combine, const lbm3_qref *q) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (combine != LBM_COMBINE_MAX && combine != LBM_COMBINE_SUM)
+    return fail(LBM_EINVAL, "unknown combine mode");
+  int rc = check_q3(q);
+  const int64_t len[3] = {h->user.nx, h->user.ny, h->user.nz};
+  const double *prof[3] = {chi_x, chi_y, chi_z};
+  for (int a = 0; a < 3 && !rc; ++a) rc = check_chi3(prof[a], (size_t)len[a], h->user.variant);
+  if (rc) return rc;
+  if (h->user.variant == LBM_VARIANT_VISC && combine == LBM_COMBINE_SUM)
+    return fail(LBM_EINVAL, "the viscosity ramp combines its profiles by max");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  free_sponge3(h);
+  void **dst[3] = {&h->chi_x, &h->chi_y, &h->chi_z};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double> v(prof[a] ? prof[a] : nullptr, prof[a] ? prof[a] + len[a] : nullptr);
+    if (!prof[a]) v.assign((size_t)len[a], 0.0);
+    rc = upload3(h, v.data(), v.size(), dst[a]);
+    if (rc) return rc;
+  }
+  h->cfg.chi_mode = combine == LBM_COMBINE_MAX ? lbm::CHI_SEP_MAX : lbm::CHI_SEP_SUM;
+  if (q) h->q = *q;
+  fill_cfg3(h);
+  return LBM_OK;
+}
+
+int lbm3_step(lbm3_handle *h, int64_t n) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  for (int64_t k = 0; k < n; ++k) {
+    hipError_t e = lbm::launch_step3(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel");
+    h->cur = 1 - h->cur;
+    h->steps += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm3_sync(lbm3_handle *h) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm3_get_populations(lbm3_handle *h, double *f) {
+  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  const size_t bytes = (size_t)h->ncell * 15 * 8;
+  double *d = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&d, bytes, h->stream), "hipMallocAsync(populations)");
+  hipError_t e = lbm::launch_getpop3(h->cfg, h->lat[h->cur], d, nullptr, nullptr, nullptr,
+                                     nullptr, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f, d, bytes, hipMemcpyDeviceToHost, h->stream);
+  (void)hipFreeAsync(d, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "get populations");
+  return LBM_OK;
+}
+
+int lbm3_set_populations(lbm3_handle *h, const double *f) {
+  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  const size_t bytes = (size_t)h->ncell * 15 * 8;
+  double *d = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&d, bytes, h->stream), "hipMallocAsync(populations)");
+  hipError_t e = hipMemcpyAsync(d, f, bytes, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = lbm::launch_setpop3(h->cfg, d, h->lat[h->cur], h->stream);
+  (void)hipFreeAsync(d, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "set populations");
+  h->steps = 0;
+  return LBM_OK;
+}
+
+int lbm3_moments(lbm3_handle *h, double *rho, double *ux, double *uy, double *uz) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  const size_t bytes = (size_t)h->ncell * 8;
+  double *d = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&d, 4 * bytes, h->stream), "hipMallocAsync(moments)");
+  double *dd[4] = {d, d + h->ncell, d + 2 * h->ncell, d + 3 * h->ncell};
+  double *outs[4] = {rho, ux, uy, uz};
+  hipError_t e = lbm::launch_getpop3(h->cfg, h->lat[h->cur], nullptr, dd[0], dd[1], dd[2], dd[3],
+                                     h->stream);
+  for (int k = 0; k < 4 && e == hipSuccess; ++k)
+    if (outs[k]) e = hipMemcpyAsync(outs[k], dd[k], bytes, hipMemcpyDeviceToHost, h->stream);
+  (void)hipFreeAsync(d, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  return LBM_OK;
+}
+
+int lbm3_steps_done(lbm3_handle *h, int64_t *steps) {
+  if (!h || !steps) return fail(LBM_EINVAL, "NULL argument");
+  *steps = h->steps;
+  return LBM_OK;
+}
+
+void lbm3_destroy(lbm3_handle *h) {
+  if (!h) return;
+  free_sponge3(h);
+  (void)hipStreamSynchronize(h->stream);
+  for (int k = 0; k < 2; ++k)
+    if (h->lat[k]) (void)hipFree(h->lat[k]);
+  delete h;
 }
 
 }  // extern "C"

@@ -115,6 +115,28 @@ int batch_multi_per_cu_f64(int k, int nw);
 int batch_multi_per_cu_f32(int k, int nw);
 int batch_multi_per_cu_f16(int k, int nw);
 
+// Three-dimensional D3Q15 step (lbm3_kernels.hip): everything a kernel
+// needs in FP64, converted per launch to the compute precision.
+struct Step3Config {
+  int nx, ny, nz;
+  int64_t pitch;         // elements between rows (slices are ny rows)
+  int64_t plane_stride;  // elements between population planes
+  int storage, variant, chi_mode;
+  double s[15];
+  double n, m;
+  double rho_b, ub[3];
+  double dcf[4];         // q_ref - base, conserved moments
+  double f16_scale;
+  const void *chi_field; // [nz][ny][pitch] compute type
+  const void *chi_x, *chi_y, *chi_z;
+};
+hipError_t launch_step3(const Step3Config &c, const void *src, void *dst, hipStream_t stream);
+hipError_t launch_init3(const Step3Config &c, const double *rho, const double *ux,
+                        const double *uy, const double *uz, void *dst, hipStream_t stream);
+hipError_t launch_setpop3(const Step3Config &c, const double *f, void *dst, hipStream_t stream);
+hipError_t launch_getpop3(const Step3Config &c, const void *src, double *f, double *rho,
+                          double *ux, double *uy, double *uz, hipStream_t stream);
+
 // Von Neumann (lbm_vn.hip).
 struct VnParamsDev {
   double s[9];

@@ -63,6 +63,21 @@ class lbm_tuning(ctypes.Structure):
                 "rows": self.rows}
 
 
+class lbm3_config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("rho_base", ctypes.c_double), ("ux_base", ctypes.c_double),
+                ("uy_base", ctypes.c_double), ("uz_base", ctypes.c_double),
+                ("s", ctypes.c_double * 15),
+                ("shift_n", ctypes.c_double), ("shift_m", ctypes.c_double),
+                ("storage", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("f16_scale", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class lbm3_qref(ctypes.Structure):
+    _fields_ = [("rho_f", ctypes.c_double), ("ux_f", ctypes.c_double), ("uy_f", ctypes.c_double),
+                ("uz_f", ctypes.c_double)]
+
+
 class lbm_vn_params(ctypes.Structure):
     _fields_ = [("s", ctypes.c_double * 9), ("shift_n", ctypes.c_double),
                 ("shift_m", ctypes.c_double), ("chi", ctypes.c_double),
@@ -129,6 +144,15 @@ def load(path: str | None = None):
         "lbm_batch_set_members": [_H, ctypes.POINTER(_H), i32],
         "lbm_init_fields_dev": [_H, vp, vp, vp],
         "lbm_batch_sync": [_H],
+        "lbm3_create": [ctypes.POINTER(lbm3_config), _DP, _DP, _DP, _DP, ctypes.POINTER(_H)],
+        "lbm3_set_sponge": [_H, _DP, ctypes.POINTER(lbm3_qref)],
+        "lbm3_set_sponge_separable": [_H, _DP, _DP, _DP, i32, ctypes.POINTER(lbm3_qref)],
+        "lbm3_step": [_H, i64],
+        "lbm3_sync": [_H],
+        "lbm3_get_populations": [_H, _DP],
+        "lbm3_set_populations": [_H, _DP],
+        "lbm3_moments": [_H, _DP, _DP, _DP, _DP],
+        "lbm3_steps_done": [_H, ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -138,6 +162,8 @@ def load(path: str | None = None):
     L.lbm_destroy.restype = None
     L.lbm_batch_destroy.argtypes = [_H]
     L.lbm_batch_destroy.restype = None
+    L.lbm3_destroy.argtypes = [_H]
+    L.lbm3_destroy.restype = None
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -601,3 +627,138 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- D3Q15 (include/lbm3.h)
+
+S3_DEFAULT = (0, 0, 0, 0, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9, 1.9)
+
+
+def make_config3(nx, ny, nz, *, s=S3_DEFAULT, storage="f32", variant="II", rho_base=1.0,
+                 ux_base=0.0, uy_base=0.0, uz_base=0.0, shift_n=0.5, shift_m=0.5,
+                 f16_scale=1e-3, stream=None):
+    c = lbm3_config()
+    c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+    c.rho_base = float(rho_base)
+    c.ux_base, c.uy_base, c.uz_base = float(ux_base), float(uy_base), float(uz_base)
+    for k in range(15):
+        c.s[k] = float(s[k])
+    c.shift_n, c.shift_m = float(shift_n), float(shift_m)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
+    c.f16_scale = float(f16_scale)
+    c.stream = _stream_ptr(stream)
+    return c
+
+
+def _qref3(q):
+    if q is None:
+        return None
+    return ctypes.byref(lbm3_qref(*[float(v) for v in q]))
+
+
+def lbm3_create(cfg, rho=None, ux=None, uy=None, uz=None):
+    L = load()
+    n = cfg.nx * cfg.ny * cfg.nz
+    keep = [_host(a, n) for a in (rho, ux, uy, uz)]
+    h = _H()
+    _check(L.lbm3_create(ctypes.byref(cfg), *[p for _a, p in keep], ctypes.byref(h)))
+    return h
+
+
+def lbm3_set_sponge(h, chi=None, qref=None):
+    _c, pc = _host(chi)
+    _check(load().lbm3_set_sponge(h, pc, _qref3(qref)))
+
+
+def lbm3_set_sponge_separable(h, chi_x=None, chi_y=None, chi_z=None, combine="max", qref=None):
+    keep = [_host(a) for a in (chi_x, chi_y, chi_z)]
+    cm = COMBINE[combine] if isinstance(combine, str) else int(combine)
+    _check(load().lbm3_set_sponge_separable(h, *[p for _a, p in keep], cm, _qref3(qref)))
+
+
+def lbm3_step(h, n=1):
+    _check(load().lbm3_step(h, int(n)))
+
+
+def lbm3_sync(h):
+    _check(load().lbm3_sync(h))
+
+
+def lbm3_get_populations(h, shape):
+    nz, ny, nx = shape
+    f = np.empty((15, nz, ny, nx), dtype=np.float64)
+    _check(load().lbm3_get_populations(h, f.ctypes.data_as(_DP)))
+    return f
+
+
+def lbm3_set_populations(h, f):
+    arr = np.ascontiguousarray(f, dtype=np.float64)
+    _check(load().lbm3_set_populations(h, arr.ctypes.data_as(_DP)))
+
+
+def lbm3_moments(h, shape):
+    out = [np.empty(shape, dtype=np.float64) for _ in range(4)]
+    _check(load().lbm3_moments(h, *[o.ctypes.data_as(_DP) for o in out]))
+    return tuple(out)
+
+
+def lbm3_steps_done(h):
+    v = ctypes.c_int64()
+    _check(load().lbm3_steps_done(h, ctypes.byref(v)))
+    return v.value
+
+
+def lbm3_destroy(h):
+    load().lbm3_destroy(h)
+
+
+class Lattice3:
+    """Owning wrapper of one D3Q15 lattice handle; host arrays [nz][ny][nx]."""
+
+    def __init__(self, nx, ny, nz, *, rho=None, ux=None, uy=None, uz=None, **cfg_kw):
+        self.cfg = make_config3(nx, ny, nz, **cfg_kw)
+        self.h = lbm3_create(self.cfg, rho, ux, uy, uz)
+        self.shape = (int(nz), int(ny), int(nx))
+
+    def set_sponge(self, chi=None, qref=None):
+        lbm3_set_sponge(self.h, chi, qref)
+
+    def set_sponge_separable(self, chi_x=None, chi_y=None, chi_z=None, combine="max",
+                             qref=None):
+        lbm3_set_sponge_separable(self.h, chi_x, chi_y, chi_z, combine, qref)
+
+    def step(self, n=1):
+        lbm3_step(self.h, n)
+
+    def sync(self):
+        lbm3_sync(self.h)
+
+    def populations(self):
+        return lbm3_get_populations(self.h, self.shape)
+
+    def set_populations(self, f):
+        lbm3_set_populations(self.h, f)
+
+    def moments(self):
+        return lbm3_moments(self.h, self.shape)
+
+    def steps_done(self):
+        return lbm3_steps_done(self.h)
+
+    def close(self):
+        if self.h is not None:
+            lbm3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

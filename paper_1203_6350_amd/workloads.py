@@ -256,6 +256,50 @@ def paper_line_source(strategy="II", thickness=0.8, u0=0.0, cells_per_unit=200, 
             "u0": u0, "t_sample": t_sample, "wavelength_cells": CS / freq}
 
 
+# ---------------------------------------------------------------- three-dimensional inputs
+
+def gaussian_pulses_3d(nx: int, ny: int, nz: int, centres, amps, halfwidths, rho0=1.0,
+                       u0=(0.0, 0.0, 0.0)):
+    """rho = rho0 + sum_k eps_k exp(-ln2 r_k^2 / b_k^2) on the periodic box
+    (minimum-image distances), u = u0 uniform. Returns (rho, ux, uy, uz) as
+    float64 [nz][ny][nx]."""
+    ax = [np.arange(n, dtype=np.float64) for n in (nx, ny, nz)]
+    rho = np.full((nz, ny, nx), float(rho0))
+    for c, a, b in zip(centres, amps, halfwidths):
+        e = []
+        for k, n in enumerate((nx, ny, nz)):
+            d = ax[k] - c[k]
+            d = d - n * np.round(d / n)
+            e.append(np.exp(-math.log(2.0) * d * d / (b * b)))
+        rho += a * e[2][:, None, None] * e[1][None, :, None] * e[0][None, None, :]
+    return (rho,) + tuple(np.full((nz, ny, nx), float(u)) for u in u0)
+
+
+def sponge_3d(chi_x: np.ndarray, chi_y: np.ndarray, chi_z: np.ndarray,
+              combine="max") -> np.ndarray:
+    """Full field [nz][ny][nx] of a separable sponge (max or sum)."""
+    a, b, c = chi_x[None, None, :], chi_y[None, :, None], chi_z[:, None, None]
+    if combine == "max":
+        return np.maximum(np.maximum(a, b), c)
+    return (a + b) + c
+
+
+def cube_d3q15(n=256, variant="II", storage="f32", u0=0.1, chi_max=0.2, width=32,
+               npulses=16):
+    """n^3 periodic box, mean flow u0 along x, ``npulses`` seeded pulses
+    (amp U[1e-4, 1e-3], b U[3, 8], centres U[width, n - width)^3), quadratic
+    ramp of ``width`` cells to chi_max on all six faces (separable, max).
+    Returns a dict: n, variant, storage, u0, fields(), profile, qref."""
+    g = rng(5)
+    centres = [tuple(g.uniform(width, n - width, size=3)) for _ in range(npulses)]
+    amps = g.uniform(1e-4, 1e-3, npulses)
+    bs = g.uniform(3.0, 8.0, npulses)
+    prof = quadratic_ramp_1d(n, width, chi_max)
+    return {"n": n, "variant": variant, "storage": storage, "u0": u0, "profile": prof,
+            "qref": (1.0, u0, 0.0, 0.0),
+            "fields": lambda: gaussian_pulses_3d(n, n, n, centres, amps, bs, 1.0, (u0, 0.0, 0.0))}
+
+
 def batch_c4(count=256, seed_index=3, max_exp=1.0):
     """Uneven domains N = round(64 * 8^U), U ~ U[0, max_exp]; chi_max U[0.01, 0.5];
     W U{8..64} clamped to N/4; Mach U[0, 0.3]; variant U{I, II, III};

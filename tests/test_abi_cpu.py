@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI that need no GPU: the library loads, exports
-every function include/lbm.h declares, and rejects bad arguments before it
-touches a device."""
+every function the headers under include/ declare, and rejects bad arguments
+before it touches a device."""
 import ctypes
 import os
 import re
@@ -11,19 +11,24 @@ import pytest
 from paper_1203_6350_amd import lbm, workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbm.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
+    names = []
+    for header in HEADERS:
+        src = open(header).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", src,
+                            flags=re.M)
     return sorted(set(names))
 
 
 def test_library_exports_every_declared_symbol():
     names = declared_functions()
     assert "lbm_create" in names and "vn_amplification" in names and len(names) >= 18
+    assert "lbm3_create" in names and "lbm3_step" in names
     L = ctypes.CDLL(lbm.LIB_PATH)
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
@@ -33,7 +38,7 @@ def test_binding_covers_header():
     L = lbm.load()
     for n in declared_functions():
         assert hasattr(L, n)
-        if n not in ("lbm_destroy", "lbm_last_error"):
+        if n not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy", "lbm3_destroy"):
             assert getattr(L, n).argtypes is not None, n
 
 
@@ -41,6 +46,24 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lbm.lbm_config) == 8 * 2 + 8 * 3 + 8 * 9 + 8 * 2 + 4 * 2 + 8 + 8
     assert ctypes.sizeof(lbm.lbm_vn_params) == 8 * 9 + 8 * 6 + 4 * 2
     assert ctypes.sizeof(lbm.lbm_qref) == 24
+    assert ctypes.sizeof(lbm.lbm3_config) == 8 * 3 + 8 * 4 + 8 * 15 + 8 * 2 + 4 * 2 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm3_qref) == 32
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(nz=-1), dict(rho_base=0.0), dict(uz_base=float("inf")),
+    dict(s=(0,) * 4 + (2.5,) + (1.9,) * 10), dict(storage=7), dict(variant=9),
+    dict(storage="f16", f16_scale=0.0), dict(shift_m=-0.5), dict(nx=2048, ny=2048, nz=1024),
+])
+def test_create3_rejects_bad_config(bad):
+    kw = dict(nx=4, ny=4, nz=4)
+    kw.update(bad)
+    nx, ny, nz = kw.pop("nx"), kw.pop("ny"), kw.pop("nz")
+    cfg = lbm.make_config3(nx, ny, nz, **kw)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm3_create(cfg)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert lbm.lbm_last_error()
 
 
 @pytest.mark.parametrize("bad", [
