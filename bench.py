@@ -47,6 +47,9 @@ KERNEL_SOURCES = {
     "one_step": [os.path.join(CSRC, f) for f in ("lbm_kernels.hip", "lbm_launch.h", "lbm_device.h")],
 }
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_f32_typeII_4096_pmc.txt")
+KERNEL_SOURCES["d3q15"] = [os.path.join(CSRC, f) for f in ("lbm3_kernels.hip", "lbm3_device.h",
+                                                            "lbm_device.h")]
+PMC_SUMMARY3 = os.path.join(ROOT, "profiles", "step3_d3q15_typeII_256cube.txt")
 
 
 def kernel_hash(family):
@@ -69,6 +72,19 @@ def counter_traffic(tuning):
     key = "%d,%d,%d" % (tuning["kernel"], tuning["block"], tuning.get("rows", 0) if tuning["kernel"] >= 2 else 0)
     b = re.search(r"scaled_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != kernel_hash(family):
+        return None
+    return float(b.group(1))
+
+
+def counter_traffic3(storage):
+    """HBM bytes per launch of the D3Q15 step kernel (256^3 workload) from
+    the committed --pmc summary, or None if the kernel sources changed."""
+    if not os.path.exists(PMC_SUMMARY3):
+        return None
+    txt = open(PMC_SUMMARY3).read()
+    m = re.search(r"d3q15_kernel_sources_sha256_16:\s*(\w+)", txt)
+    b = re.search(r"scaled_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % storage, txt)
+    if not m or not b or m.group(1) != kernel_hash("d3q15"):
         return None
     return float(b.group(1))
 
@@ -514,6 +530,7 @@ def d3q15_leg(lbm, wl, torch, n=256, steps=200, warmup=10):
         out[st] = {"mlups": cells / ms / 1e3, "ms_per_step": ms, "bytes_per_cell": b,
                    "hbm_gbps": b * cells / (ms * 1e-3) / 1e9,
                    "hbm_frac": b * cells / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                   "traffic": counter_traffic3(st) if n == 256 else None,
                    "max_abs_rho_dev": float(np.abs(rho - 1.0).max()),
                    "finite": bool(np.isfinite(rho).all())}
     return out
