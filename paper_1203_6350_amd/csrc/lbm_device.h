@@ -128,7 +128,13 @@ __device__ __forceinline__ void ref_moments(const CollideParams<C> &p, C mref[9]
 // One collision in deviation form; g holds the pre-collision deviations on
 // entry and the post-collision deviations on return. mref comes from
 // ref_moments (read by Types I and II only).
-template <typename C, int VAR>
+//
+// A conserved moment (k < 3) whose rate is exactly 0 skips the relaxation
+// (its value passes unchanged), in every kernel; SC0 = true states at
+// compile time that all three conserved rates are 0 (the paper's MRT
+// default), which drops the run-time test and the relaxation arithmetic of
+// those moments.
+template <typename C, int VAR, bool SC0 = false>
 __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p,
                                         const C mref[9]) {
   // ---- dm = M g (Appendix A.1)
@@ -171,12 +177,24 @@ __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p
   for (int k = 0; k < 9; ++k) {
     C sk = p.s[k];
     if (VAR == V_VISC && k >= 3) sk = fmaC(C(1) - sk, chi, sk);
-    mp[k] = fmaC(sk, meq[k] - dm[k], dm[k]);
+    if (k < 3)
+      mp[k] = (SC0 || sk == C(0)) ? dm[k] : fmaC(sk, meq[k] - dm[k], dm[k]);
+    else
+      mp[k] = fmaC(sk, meq[k] - dm[k], dm[k]);
   }
-  if (VAR == V_I || VAR == V_II) {
+  if (VAR == V_I) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
-      mp[k] = fmaC(chi, mref[k] - (VAR == V_I ? dm[k] : meq[k]), mp[k]);
+    for (int k = 0; k < 9; ++k) mp[k] = fmaC(chi, mref[k] - dm[k], mp[k]);
+  } else if (VAR == V_II) {
+    // rows 5 and 6 of m^eq (and of m^ref) are -jx and -jy: their damping
+    // differences are those of rows 1 and 2 with the sign flipped
+    C e[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e[k] = mref[k] - meq[k];
+    e[5] = -e[1];
+    e[6] = -e[2];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mp[k] = fmaC(chi, e[k], mp[k]);
   } else if (VAR == V_III) {
     // e = L (dc^f - dc*), L c = (rho, jx, jy, -2 rho, rho, -jx, -jy, 0, 0)
     const C a = p.dcf0 - dr, bx = p.dcf1 - djx, by = p.dcf2 - djy;
@@ -215,7 +233,7 @@ template <typename C, int VAR>
 __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p) {
   C mref[9];
   if (VAR == V_I || VAR == V_II) ref_moments(p, mref);
-  collide<C, VAR>(g, chi, p, mref);
+  collide<C, VAR, false>(g, chi, p, mref);
 }
 
 // Storage traits: load/store one population element with the per-direction

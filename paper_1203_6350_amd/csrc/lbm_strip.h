@@ -48,6 +48,12 @@ namespace lbm {
 // members may each use another form); the other values are ChiMode.
 constexpr int CHI_RUNTIME = 4;
 
+// The VAR parameter of the strip kernels is a Variant, optionally with
+// V_SC0 set: the launch's conserved rates s_0, s_1, s_2 are all 0 in the
+// compute precision (collide's SC0).
+constexpr int V_MASK = 7;
+constexpr int V_SC0 = 8;
+
 template <int K>
 constexpr int strip_width() {
   return 64 - 2 * K;
@@ -251,7 +257,7 @@ struct StripCtx {
     // the sponge input of row a + 1 is read after this use, so waiting for
     // it does not hold up this row
     if (left > 2) st.craw[md<6>(P + 1)] = chi_raw(r_next);
-    collide<C, VAR>(g, chi1, p, mref);
+    collide<C, VAR & V_MASK, (VAR & V_SC0) != 0>(g, chi1, p, mref);
     chain<P, J, 2>(st, g, a);
   }
 
@@ -268,7 +274,7 @@ struct StripCtx {
       pull<C>(st.b256[j - 2][md<3>(P - j - 1)], st.b013[j - 2][md<2>(P - j)], g[4], g[7], g[8],
               o);
       keep<j - 1, P - (j - 1)>(st, g);
-      collide<C, VAR>(o, chi_of(st.craw[md<6>(P - j)]), p, mref);
+      collide<C, VAR & V_MASK, (VAR & V_SC0) != 0>(o, chi_of(st.craw[md<6>(P - j)]), p, mref);
       if constexpr (j == K) {
         if (store_lane) {
 #pragma unroll
@@ -322,7 +328,7 @@ __device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S
     c.inv_scale[i] = inv_scale[i];
   }
   c.p = p;
-  if (VAR == V_I || VAR == V_II) ref_moments(p, c.mref);
+  if ((VAR & V_MASK) == V_I || (VAR & V_MASK) == V_II) ref_moments(p, c.mref);
 }
 
 // The row loop of one strip over R output rows from Y0 on.
@@ -567,12 +573,24 @@ hipError_t launch_multi_storage(const StepConfig &c, int k, const void *src, voi
     case CHI_SEP_SUM: return launch_multi<S, VAR, CHI_SEP_SUM>(c, k, src, dst, s); \
   }                                                                           \
   return hipErrorInvalidValue;
-  switch (c.variant) {
-    case V_NONE: { LBM_CHI(V_NONE) }
-    case V_I: { LBM_CHI(V_I) }
-    case V_II: { LBM_CHI(V_II) }
-    case V_III: { LBM_CHI(V_III) }
-    case V_VISC: { LBM_CHI(V_VISC) }
+  typedef typename Store<S>::C C;
+  const bool sc0 = C(c.s[0]) == C(0) && C(c.s[1]) == C(0) && C(c.s[2]) == C(0);
+  if (sc0) {
+    switch (c.variant) {
+      case V_NONE: { LBM_CHI(V_NONE | V_SC0) }
+      case V_I: { LBM_CHI(V_I | V_SC0) }
+      case V_II: { LBM_CHI(V_II | V_SC0) }
+      case V_III: { LBM_CHI(V_III | V_SC0) }
+      case V_VISC: { LBM_CHI(V_VISC | V_SC0) }
+    }
+  } else {
+    switch (c.variant) {
+      case V_NONE: { LBM_CHI(V_NONE) }
+      case V_I: { LBM_CHI(V_I) }
+      case V_II: { LBM_CHI(V_II) }
+      case V_III: { LBM_CHI(V_III) }
+      case V_VISC: { LBM_CHI(V_VISC) }
+    }
   }
 #undef LBM_CHI
   return hipErrorInvalidValue;
