@@ -99,12 +99,15 @@ __device__ __forceinline__ void meq_delta(C dr, C djx, C djy, C rho_b, C ubx,
                                           C uby, C out[9]) {
   const C rho = rho_b + dr;
   const C inv = recip(rho);
-  const C vx = djx - ubx * dr;
-  const C vy = djy - uby * dr;
-  // d(jx^2/rho), d(jy^2/rho), d(jx jy/rho)
-  const C qxx = fmaC(vx * vx, inv, ubx * (C(2) * djx - ubx * dr));
-  const C qyy = fmaC(vy * vy, inv, uby * (C(2) * djy - uby * dr));
-  const C qxy = fmaC(vx * vy, inv, ubx * djy + uby * djx - ubx * uby * dr);
+  // v = dj - u_b dr, so that j = u_b rho + v and
+  //   d(jx^2/rho) = ubx (djx + vx) + vx^2/rho
+  //   d(jy^2/rho) = uby (djy + vy) + vy^2/rho
+  //   d(jx jy/rho) = ubx djy + uby vx + vx vy/rho
+  const C vx = fmaC(-ubx, dr, djx);
+  const C vy = fmaC(-uby, dr, djy);
+  const C qxx = fmaC(vx * vx, inv, ubx * (djx + vx));
+  const C qyy = fmaC(vy * vy, inv, uby * (djy + vy));
+  const C qxy = fmaC(vx * vy, inv, fmaC(ubx, djy, uby * vx));
   const C tr = qxx + qyy;
   out[0] = dr;
   out[1] = djx;
@@ -130,11 +133,13 @@ __device__ __forceinline__ void ref_moments(const CollideParams<C> &p, C mref[9]
 // ref_moments (read by Types I and II only).
 //
 // A conserved moment (k < 3) whose rate is exactly 0 skips the relaxation
-// (its value passes unchanged), in every kernel; SC0 = true states at
-// compile time that all three conserved rates are 0 (the paper's MRT
-// default), which drops the run-time test and the relaxation arithmetic of
-// those moments.
-template <typename C, int VAR, bool SC0 = false>
+// (its value passes unchanged), in every kernel. DEF = true states at
+// compile time that the launch has the paper's MRT defaults in this
+// respect: all three conserved rates are 0 and the two shift parameters are
+// equal (n = m). That drops the run-time rate test, the relaxation
+// arithmetic of those moments and the second reciprocal; the results are
+// the same bits as without it.
+template <typename C, int VAR, bool DEF = false>
 __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p,
                                         const C mref[9]) {
   // ---- dm = M g (Appendix A.1)
@@ -155,73 +160,135 @@ __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p
   dm[7] = ax - ay;
   dm[8] = (g[5] + g[7]) - (g[6] + g[8]);
 
-  // ---- shifted conserved quantities dc*
+  // ---- shifted conserved quantities dc* = (dc + n chi dc^f)/(1 + n chi)
+  // (m for j), written as dc + (n chi/(1 + n chi)) (dc^f - dc); the
+  // remainder dc^f - dc* = (dc^f - dc)/(1 + n chi) is what the damping of
+  // the conserved rows needs.
   C dr = dm[0], djx = dm[1], djy = dm[2];
+  C d0 = C(0), d1 = C(0), d2 = C(0), inv_n = C(1), inv_m = C(1);
   if (VAR != V_NONE && VAR != V_VISC) {
-    const C nchi = p.n * chi, mchi = p.m * chi;
-    const C inv_n = recip(C(1) + nchi);
-    const C inv_m = p.n == p.m ? inv_n : recip(C(1) + mchi);
-    dr = fmaC(nchi, p.dcf0, dm[0]) * inv_n;
-    djx = fmaC(mchi, p.dcf1, dm[1]) * inv_m;
-    djy = fmaC(mchi, p.dcf2, dm[2]) * inv_m;
+    d0 = p.dcf0 - dm[0];
+    d1 = p.dcf1 - dm[1];
+    d2 = p.dcf2 - dm[2];
+    const C nchi = p.n * chi, mchi = DEF ? nchi : p.m * chi;
+    inv_n = recip(C(1) + nchi);
+    inv_m = (DEF || p.n == p.m) ? inv_n : recip(C(1) + mchi);
+    const C fn = nchi * inv_n, fm = mchi * inv_m;
+    dr = fmaC(fn, d0, dm[0]);
+    djx = fmaC(fm, d1, dm[1]);
+    djy = fmaC(fm, d2, dm[2]);
   }
 
   // ---- equilibrium moments at the shifted state
   C meq[9];
   meq_delta(dr, djx, djy, p.rho_b, p.ubx, p.uby, meq);
 
-  // ---- relaxation, then the damping d = chi e (Gamma = chi I) added with
-  // one fused multiply-add per moment
-  C mp[9];
+  // ---- relaxation and damping, m' = dm + S o (dm^eq* - dm) + chi e
+  // (Gamma = chi I), delivered as a_k = m'_k / D_k for the back-transform
+  // M^-1 = M^T D^-1, D = diag(9, 6, 6, 36, 36, 12, 12, 4, 4).
+  constexpr double DINV[9] = {1.0 / 9.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 36.0, 1.0 / 36.0,
+                              1.0 / 12.0, 1.0 / 12.0, 0.25, 0.25};
+  C a[9];
+  // conserved rows: a zero rate leaves the moment as it is
+  {
+    C mc[3];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    C sk = p.s[k];
-    if (VAR == V_VISC && k >= 3) sk = fmaC(C(1) - sk, chi, sk);
-    if (k < 3)
-      mp[k] = (SC0 || sk == C(0)) ? dm[k] : fmaC(sk, meq[k] - dm[k], dm[k]);
-    else
-      mp[k] = fmaC(sk, meq[k] - dm[k], dm[k]);
+    for (int k = 0; k < 3; ++k) {
+      const C sk = p.s[k];
+      mc[k] = (DEF || sk == C(0)) ? dm[k] : fmaC(sk, meq[k] - dm[k], dm[k]);
+    }
+    if (VAR == V_I) {
+      // rows 0-2 of m^ref - m are dc^f - dc
+      mc[0] = fmaC(chi, d0, mc[0]);
+      mc[1] = fmaC(chi, d1, mc[1]);
+      mc[2] = fmaC(chi, d2, mc[2]);
+    } else if (VAR == V_II || VAR == V_III) {
+      // rows 0-2 of m^ref - m^eq* (II) and of L (dc^f - dc*) (III) are
+      // dc^f - dc* = (dc^f - dc)/(1 + n chi) (m for j)
+      mc[0] = fmaC(chi * inv_n, d0, mc[0]);
+      mc[1] = fmaC(chi * inv_m, d1, mc[1]);
+      mc[2] = fmaC(chi * inv_m, d2, mc[2]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] = mc[k] * C(DINV[k]);
   }
-  if (VAR == V_I) {
+  // non-conserved rows, one rate per row (the viscosity ramp raises it per
+  // cell). In FP32: a_k = ((1 - s_k)/D_k) dm_k + (s_k/D_k) dm^eq*_k +
+  // chi e_k / D_k, which saves the separate scaling; in FP64 (twice the
+  // registers per value) the relaxed moment is formed first and then
+  // scaled. Within a precision every variant takes the same form, so that
+  // where chi = 0 they all give the bits of the undamped scheme.
+  if (sizeof(C) == 8) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) mp[k] = fmaC(chi, mref[k] - dm[k], mp[k]);
-  } else if (VAR == V_II) {
-    // rows 5 and 6 of m^eq (and of m^ref) are -jx and -jy: their damping
-    // differences are those of rows 1 and 2 with the sign flipped
+    for (int k = 3; k < 9; ++k) {
+      C sk = p.s[k];
+      if (VAR == V_VISC) sk = fmaC(C(1) - sk, chi, sk);
+      C m = fmaC(sk, meq[k] - dm[k], dm[k]);
+      if (VAR == V_I) {
+        m = fmaC(chi, mref[k] - dm[k], m);
+      } else if (VAR == V_II) {
+        if (k == 5) m = fmaC(-chi * inv_m, d1, m);
+        else if (k == 6) m = fmaC(-chi * inv_m, d2, m);
+        else m = fmaC(chi, mref[k] - meq[k], m);
+      } else if (VAR == V_III) {
+        if (k == 3) m = fmaC(C(-2) * chi * inv_n, d0, m);
+        else if (k == 4) m = fmaC(chi * inv_n, d0, m);
+        else if (k == 5) m = fmaC(-chi * inv_m, d1, m);
+        else if (k == 6) m = fmaC(-chi * inv_m, d2, m);
+      }
+      a[k] = m * C(DINV[k]);
+    }
+  } else {
     C e[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) e[k] = mref[k] - meq[k];
-    e[5] = -e[1];
-    e[6] = -e[2];
+    for (int k = 3; k < 9; ++k) e[k] = C(0);
+    if (VAR == V_I) {
+      const C c36 = chi * C(DINV[3]), c12 = chi * C(DINV[5]), c4 = chi * C(DINV[7]);
+      e[3] = c36 * (mref[3] - dm[3]);
+      e[4] = c36 * (mref[4] - dm[4]);
+      e[5] = c12 * (mref[5] - dm[5]);
+      e[6] = c12 * (mref[6] - dm[6]);
+      e[7] = c4 * (mref[7] - dm[7]);
+      e[8] = c4 * (mref[8] - dm[8]);
+    } else if (VAR == V_II) {
+      // rows 5 and 6 of m^eq and m^ref are -jx and -jy: their differences
+      // are those of rows 1 and 2 with the sign flipped
+      const C c36 = chi * C(DINV[3]), c4 = chi * C(DINV[7]), cm12 = chi * inv_m * C(DINV[5]);
+      e[3] = c36 * (mref[3] - meq[3]);
+      e[4] = c36 * (mref[4] - meq[4]);
+      e[5] = -cm12 * d1;
+      e[6] = -cm12 * d2;
+      e[7] = c4 * (mref[7] - meq[7]);
+      e[8] = c4 * (mref[8] - meq[8]);
+    } else if (VAR == V_III) {
+      // L (dc^f - dc*), L c = (rho, jx, jy, -2 rho, rho, -jx, -jy, 0, 0)
+      const C c36 = chi * inv_n * C(DINV[3]), cm12 = chi * inv_m * C(DINV[5]);
+      e[3] = C(-2) * c36 * d0;
+      e[4] = c36 * d0;
+      e[5] = -cm12 * d1;
+      e[6] = -cm12 * d2;
+    }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) mp[k] = fmaC(chi, e[k], mp[k]);
-  } else if (VAR == V_III) {
-    // e = L (dc^f - dc*), L c = (rho, jx, jy, -2 rho, rho, -jx, -jy, 0, 0)
-    const C a = p.dcf0 - dr, bx = p.dcf1 - djx, by = p.dcf2 - djy;
-    mp[0] = fmaC(chi, a, mp[0]);
-    mp[1] = fmaC(chi, bx, mp[1]);
-    mp[2] = fmaC(chi, by, mp[2]);
-    mp[3] = fmaC(chi, C(-2) * a, mp[3]);
-    mp[4] = fmaC(chi, a, mp[4]);
-    mp[5] = fmaC(chi, -bx, mp[5]);
-    mp[6] = fmaC(chi, -by, mp[6]);
+    for (int k = 3; k < 9; ++k) {
+      C sk = p.s[k];
+      if (VAR == V_VISC) sk = fmaC(C(1) - sk, chi, sk);
+      a[k] = fmaC((C(1) - sk) * C(DINV[k]), dm[k], fmaC(sk * C(DINV[k]), meq[k], e[k]));
+    }
   }
 
-  // ---- g' = M^-1 dm'
-  const C a0 = mp[0] * C(1.0 / 9.0);
-  const C a1 = mp[1] * C(1.0 / 6.0), a2 = mp[2] * C(1.0 / 6.0);
-  const C a3 = mp[3] * C(1.0 / 36.0), a4 = mp[4] * C(1.0 / 36.0);
-  const C a5 = mp[5] * C(1.0 / 12.0), a6 = mp[6] * C(1.0 / 12.0);
-  const C a7 = mp[7] * C(0.25), a8 = mp[8] * C(0.25);
+  // ---- g' = M^-1 dm' = M^T a
+  const C a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4], a5 = a[5], a6 = a[6],
+          a7 = a[7], a8 = a[8];
   const C pa = a0 - a3 - C(2) * a4;   // shared by the axis directions
   const C pd = a0 + C(2) * a3 + a4;   // shared by the diagonal directions
   const C tx = a1 - C(2) * a5, ty = a2 - C(2) * a6;
   const C bx = a1 + a5, by = a2 + a6;
+  const C pxa = pa + a7, pya = pa - a7;
   g[0] = a0 - C(4) * a3 + C(4) * a4;
-  g[1] = (pa + tx) + a7;
-  g[2] = (pa + ty) - a7;
-  g[3] = (pa - tx) + a7;
-  g[4] = (pa - ty) - a7;
+  g[1] = pxa + tx;
+  g[2] = pya + ty;
+  g[3] = pxa - tx;
+  g[4] = pya - ty;
   g[5] = (pd + bx) + (by + a8);
   g[6] = (pd - bx) + (by - a8);
   g[7] = (pd - bx) - (by - a8);
