@@ -32,12 +32,12 @@ PEAK_HBM_GBPS = 8000.0
 # FP32 (and FP64) vector FMA issue of MI355X without packed FP32 math, which
 # this library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 PEAK_VALU_TFLOPS = 78.6
-# Arithmetic of one cell update in the deviation form the kernels use (FMA =
-# 2 flop): M g (31), shifted conserved moments (13), equilibrium moments
-# (36), relaxation (27), damping term (27 for Types I and II, 18 for III),
-# the sponge value (1) and M^-1 (45); no damping and no shift without a
-# sponge term, a ramp of six rates instead for the viscosity strategy.
-FLOPS_PER_UPDATE = {"none": 139, "I": 180, "II": 180, "III": 171, "visc": 152}
+# Arithmetic of one cell update (FMA = 2 flop) as the collision executes it
+# with the default parameters (conserved rates 0, n = m), counted on the
+# compiled loop of the four-step kernel: M g, the shifted conserved moments,
+# the equilibrium deviations, relaxation and damping folded with D^-1, and
+# M^T; the one reciprocal of rho per cell and of 1 + n chi per row count once.
+FLOPS_PER_UPDATE = {"none": 118, "I": 148, "II": 146, "III": 140, "visc": 129}
 METRIC = "D2Q9 MRT+sponge MLUPS & %HBM peak; batched-served vs plain MLUPS, p99 latency"
 CSRC = os.path.join(ROOT, "paper_1203_6350_amd", "csrc")
 # sources of the two step-kernel families: the K-step strip kernel and the

@@ -49,10 +49,11 @@ namespace lbm {
 constexpr int CHI_RUNTIME = 4;
 
 // The VAR parameter of the strip kernels is a Variant, optionally with
-// V_SC0 set: the launch's conserved rates s_0, s_1, s_2 are all 0 in the
-// compute precision (collide's SC0).
+// V_DEF set: in the compute precision the launch's conserved rates s_0,
+// s_1, s_2 are all 0 and its shift parameters n and m are equal (collide's
+// DEF).
 constexpr int V_MASK = 7;
-constexpr int V_SC0 = 8;
+constexpr int V_DEF = 8;
 
 template <int K>
 constexpr int strip_width() {
@@ -257,7 +258,7 @@ struct StripCtx {
     // the sponge input of row a + 1 is read after this use, so waiting for
     // it does not hold up this row
     if (left > 2) st.craw[md<6>(P + 1)] = chi_raw(r_next);
-    collide<C, VAR & V_MASK, (VAR & V_SC0) != 0>(g, chi1, p, mref);
+    collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(g, chi1, p, mref);
     chain<P, J, 2>(st, g, a);
   }
 
@@ -274,7 +275,7 @@ struct StripCtx {
       pull<C>(st.b256[j - 2][md<3>(P - j - 1)], st.b013[j - 2][md<2>(P - j)], g[4], g[7], g[8],
               o);
       keep<j - 1, P - (j - 1)>(st, g);
-      collide<C, VAR & V_MASK, (VAR & V_SC0) != 0>(o, chi_of(st.craw[md<6>(P - j)]), p, mref);
+      collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(o, chi_of(st.craw[md<6>(P - j)]), p, mref);
       if constexpr (j == K) {
         if (store_lane) {
 #pragma unroll
@@ -424,11 +425,12 @@ __global__ __launch_bounds__(512) void step_multi_strip(
 // runs the strip loop of its item with the member's own size, rates,
 // variant, sponge and parity. Launch j of a tick advances the members that
 // take at least (j + 1) K steps in it.
+// FP32 compute: registers for three waves per SIMD (the run-time variant
+// and rate switches would otherwise take it to two).
 template <typename S, int K>
-__global__ __launch_bounds__(512) void batch_multi_strip(const BatchDomain *__restrict__ doms,
-                                                         const int4 *__restrict__ items,
-                                                         const int *__restrict__ nitems_dev,
-                                                         int j) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
+void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restrict__ items,
+                       const int *__restrict__ nitems_dev, int j) {
   typedef typename Store<S>::C C;
   const int nitems = *nitems_dev;
   const int nw = blockDim.x >> 6;
@@ -574,14 +576,15 @@ hipError_t launch_multi_storage(const StepConfig &c, int k, const void *src, voi
   }                                                                           \
   return hipErrorInvalidValue;
   typedef typename Store<S>::C C;
-  const bool sc0 = C(c.s[0]) == C(0) && C(c.s[1]) == C(0) && C(c.s[2]) == C(0);
-  if (sc0) {
+  const bool def = C(c.s[0]) == C(0) && C(c.s[1]) == C(0) && C(c.s[2]) == C(0) &&
+                   C(c.n) == C(c.m);
+  if (def) {
     switch (c.variant) {
-      case V_NONE: { LBM_CHI(V_NONE | V_SC0) }
-      case V_I: { LBM_CHI(V_I | V_SC0) }
-      case V_II: { LBM_CHI(V_II | V_SC0) }
-      case V_III: { LBM_CHI(V_III | V_SC0) }
-      case V_VISC: { LBM_CHI(V_VISC | V_SC0) }
+      case V_NONE: { LBM_CHI(V_NONE | V_DEF) }
+      case V_I: { LBM_CHI(V_I | V_DEF) }
+      case V_II: { LBM_CHI(V_II | V_DEF) }
+      case V_III: { LBM_CHI(V_III | V_DEF) }
+      case V_VISC: { LBM_CHI(V_VISC | V_DEF) }
     }
   } else {
     switch (c.variant) {
