@@ -544,7 +544,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16"])
     ap.add_argument("--variants", default="II,I,III")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--no-storages", action="store_true")
     ap.add_argument("--no-qref", action="store_true")
     ap.add_argument("--no-line-source", action="store_true")

@@ -426,16 +426,18 @@ def test_multi_step_kernel_every_variant_and_sponge_form(storage, variant):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("rates", ["mrt", "bgk", "mixed"])
+@pytest.mark.parametrize("rates", ["mrt", "bgk", "mixed", "mrt_n_ne_m"])
 def test_multi_step_kernel_conserved_rates(storage, rates):
-    """The strip kernels have a form for zero conserved rates (the MRT
-    default) and a general one; a zero conserved rate leaves its moment
-    unchanged in every kernel, so both forms are bit-identical to the
-    one-cell-per-thread kernel, and FP64 matches the oracle."""
+    """The strip kernels have a form for the paper's defaults (zero
+    conserved rates, n = m) and a general one; a zero conserved rate leaves
+    its moment unchanged in every kernel, so both forms are bit-identical to
+    the one-cell-per-thread kernel, and FP64 matches the oracle."""
     nx, ny, steps = 97, 23, 10
     S = {"mrt": (0.0, 0.0, 0.0, 1.1, 1.2, 1.3, 1.4, 1.5, 1.6),
          "bgk": (1.7,) * 9,
-         "mixed": (0.0, 0.6, 0.0, 1.1, 1.2, 1.3, 1.4, 1.5, 1.6)}[rates]
+         "mixed": (0.0, 0.6, 0.0, 1.1, 1.2, 1.3, 1.4, 1.5, 1.6),
+         "mrt_n_ne_m": (0.0, 0.0, 0.0, 1.1, 1.2, 1.3, 1.4, 1.5, 1.6)}[rates]
+    nm = dict(shift_n=0.3, shift_m=0.8) if rates == "mrt_n_ne_m" else {}
     say("case: conserved rates", storage, rates)
     rho, ux, uy, chi = random_case(nx, ny, 13)
     q = (1.0005, 0.045, -0.003)
@@ -445,7 +447,7 @@ def test_multi_step_kernel_conserved_rates(storage, rates):
         for t in (dict(kernel=0, block=64), dict(kernel=2, block=128, rows=5),
                   dict(kernel=3, block=256, rows=3), dict(kernel=4, block=64, rows=0)):
             lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant=variant,
-                              s=S, ux_base=0.04, f16_scale=1e-3)
+                              s=S, ux_base=0.04, f16_scale=1e-3, **nm)
             lat.set_sponge(c, q)
             lat.set_tuning(**t)
             lat.step(steps)
@@ -457,7 +459,8 @@ def test_multi_step_kernel_conserved_rates(storage, rates):
             assert (st == states[0]).all(), variant
         if storage == "f64":
             ref = oracle.step(oracle.feq_field(rho, ux, uy), steps, s=S, chi=c, qref=q,
-                              variant=variant)
+                              variant=variant, n=nm.get("shift_n", 0.5),
+                              m=nm.get("shift_m", 0.5))
             assert rel_max(got, ref) <= 1e-12, variant
 
 
