@@ -74,6 +74,12 @@ int lbm3_set_populations(lbm3_handle *h, const double *f);
  * may be NULL); synchronises. */
 int lbm3_moments(lbm3_handle *h, double *rho, double *ux, double *uy, double *uz);
 
+/* Workgroup size of the step (one cell per thread, a workgroup covers
+ * consecutive cells of one row): 64..512 in steps of 64, default 256
+ * (LBM_EINVAL otherwise). Every size gives bit-identical results. */
+int lbm3_set_tuning(lbm3_handle *h, int32_t block);
+int lbm3_get_tuning(lbm3_handle *h, int32_t *block);
+
 /* Number of steps taken since creation or the last lbm3_set_populations. */
 int lbm3_steps_done(lbm3_handle *h, int64_t *steps);
 

@@ -86,19 +86,20 @@ __device__ __forceinline__ C chi3_at(const C *field, const C *cx, const C *cy, c
   return (a + b) + d;
 }
 
-// One step, one cell per thread; a block covers 256 consecutive cells of one
-// row, blocks are numbered row-major (x, then y, then z) so consecutive
-// blocks stream consecutive memory.
+// One step, one cell per thread; a block covers consecutive cells of one row
+// (64..512), blocks are numbered row-major (x, then y, then z) so
+// consecutive blocks stream consecutive memory.
 template <typename S, int VAR, int CHI>
-__global__ __launch_bounds__(256) void step3_kernel(
+__global__ __launch_bounds__(512) void step3_kernel(
     const S *__restrict__ src, S *__restrict__ dst, Lat3<S> L,
     CollideParams3<typename Store<S>::C> p, const typename Store<S>::C *__restrict__ chi_field,
     const typename Store<S>::C *__restrict__ chix, const typename Store<S>::C *__restrict__ chiy,
     const typename Store<S>::C *__restrict__ chiz) {
   typedef typename Store<S>::C C;
-  const int bpr = (L.nx + 255) / 256;
+  const int bx = blockDim.x;
+  const int bpr = (L.nx + bx - 1) / bx;
   const int row = blockIdx.x / bpr;  // y + ny z
-  const int x = (blockIdx.x - row * bpr) * 256 + threadIdx.x;
+  const int x = (blockIdx.x - row * bpr) * bx + threadIdx.x;
   if (x >= L.nx) return;
   const int z = row / L.ny, y = row - z * L.ny;
   const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
@@ -139,9 +140,11 @@ static hipError_t launch_step3_t(const Step3Config &c, const void *src, void *ds
   typedef typename Store<S>::C C;
   const Lat3<S> L = make_lat3<S>(c);
   const CollideParams3<C> p = make_params3<C>(c);
-  const int64_t blocks = (int64_t)((c.nx + 255) / 256) * c.ny * c.nz;
+  const int bx = c.block;
+  if (bx < 64 || bx > 512 || bx % 64) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t)((c.nx + bx - 1) / bx) * c.ny * c.nz;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  step3_kernel<S, VAR, CHI><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(
+  step3_kernel<S, VAR, CHI><<<dim3((unsigned)blocks), dim3(bx), 0, stream>>>(
       (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
       (const C *)c.chi_y, (const C *)c.chi_z);
   return hipGetLastError();

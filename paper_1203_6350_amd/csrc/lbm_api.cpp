@@ -1399,6 +1399,7 @@ int lbm3_create(const lbm3_config *cfg, const double *rho, const double *ux, con
   h->cfg.plane_stride = round_up(h->ncell, 256 / eb);
   h->cfg.chi_mode = lbm::CHI_ZERO;
   h->lat_bytes = (size_t)h->cfg.plane_stride * 15 * eb;
+  h->cfg.block = 256;
   fill_cfg3(h);
   for (int k = 0; k < 2; ++k) {
     hipError_t e = hipMalloc(&h->lat[k], h->lat_bytes);
@@ -1536,6 +1537,20 @@ int lbm3_moments(lbm3_handle *h, double *rho, double *ux, double *uy, double *uz
   (void)hipFreeAsync(d, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(e, "moments");
+  return LBM_OK;
+}
+
+int lbm3_set_tuning(lbm3_handle *h, int32_t block) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (block < 64 || block > 512 || block % 64)
+    return fail(LBM_EINVAL, "block must be 64..512 in steps of 64");
+  h->cfg.block = block;
+  return LBM_OK;
+}
+
+int lbm3_get_tuning(lbm3_handle *h, int32_t *block) {
+  if (!h || !block) return fail(LBM_EINVAL, "NULL argument");
+  *block = h->cfg.block;
   return LBM_OK;
 }
 

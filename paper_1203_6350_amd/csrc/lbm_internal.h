@@ -129,6 +129,7 @@ struct Step3Config {
   double f16_scale;
   const void *chi_field; // [nz][ny][pitch] compute type
   const void *chi_x, *chi_y, *chi_z;
+  int block;             // threads per workgroup, 64..512, a multiple of 64
 };
 hipError_t launch_step3(const Step3Config &c, const void *src, void *dst, hipStream_t stream);
 hipError_t launch_init3(const Step3Config &c, const double *rho, const double *ux,
