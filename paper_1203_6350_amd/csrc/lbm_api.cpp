@@ -799,9 +799,10 @@ struct lbm_batch {
   int *d_nitems = nullptr;
   int nitems = 0;
   size_t item_cap = 0;
+  bool multi_def = false;  // every member takes the default form of the collision
   // graphs keyed by (K or 0, K-step launches or ticks, remainder launches,
-  // tile workgroups per CU, strip workgroup waves)
-  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
+  // tile workgroups per CU, strip workgroup waves, default form)
+  std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -834,6 +835,16 @@ void fill_domain(const lbm_handle *h, int stop_at, lbm::BatchDomain &d) {
   }
 }
 
+// The member's parameters allow the collision's default form: conserved
+// rates 0 and n = m, compared in the compute precision as the kernels see
+// them (FP64 storage computes in FP64, the others in FP32).
+bool default_form(const lbm::StepConfig &c) {
+  if (c.storage == LBM_STORAGE_F64)
+    return c.s[0] == 0.0 && c.s[1] == 0.0 && c.s[2] == 0.0 && c.n == c.m;
+  return (float)c.s[0] == 0.0f && (float)c.s[1] == 0.0f && (float)c.s[2] == 0.0f &&
+         (float)c.n == (float)c.m;
+}
+
 void free_graphs(lbm_batch *b) {
   for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
@@ -844,7 +855,8 @@ void free_graphs(lbm_batch *b) {
 // nsingle-1; with K-step launches these take the members' remainders).
 int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, hipGraphExec_t *out) {
   const int grid = b->cus * b->blocks_per_cu;
-  const auto key = std::make_tuple(K, nmulti, nsingle, b->blocks_per_cu, K ? b->multi_nw : 0);
+  const auto key = std::make_tuple(K, nmulti, nsingle, b->blocks_per_cu, K ? b->multi_nw : 0,
+                                   K ? (int)b->multi_def : 0);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -853,8 +865,8 @@ int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, hipGraphExec_t *ou
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   hipError_t e = hipSuccess;
   for (int j = 0; j < nmulti && e == hipSuccess; ++j)
-    e = lbm::launch_batch_multi(b->storage, K, b->multi_nw, b->d_doms, b->d_items,
-                                b->d_nitems, b->multi_grid, j, b->stream);
+    e = lbm::launch_batch_multi(b->storage, K, b->multi_nw, b->multi_def, b->d_doms,
+                                b->d_items, b->d_nitems, b->multi_grid, j, b->stream);
   for (int k = 0; k < nsingle && e == hipSuccess; ++k)
     e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, K, b->stream);
   hipGraph_t g = nullptr;
@@ -922,7 +934,9 @@ int build_items(lbm_batch *b) {
   if (!b->multi_k) return LBM_OK;
   const int W = 64 - 2 * b->multi_k;
   const int nw = b->multi_nw;
-  const int per_cu = lbm::batch_multi_per_cu(b->storage, b->multi_k, nw);
+  b->multi_def = true;
+  for (const lbm_handle *h : b->members) b->multi_def = b->multi_def && default_form(h->cfg);
+  const int per_cu = lbm::batch_multi_per_cu(b->storage, b->multi_k, nw, b->multi_def);
   if (per_cu < 1) return fail(LBM_EDEVICE, "the strip kernel does not fit on a compute unit");
   b->multi_grid = b->cus * per_cu;
   int64_t group_rows = 0;

@@ -115,22 +115,22 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_multi(int storage, int k, int nw, const BatchDomain *doms,
+hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
                               const int4 *items, const int *nitems, int grid, int j,
                               hipStream_t stream) {
   switch (storage) {
-    case 0: return launch_batch_multi_f64(k, nw, doms, items, nitems, grid, j, stream);
-    case 1: return launch_batch_multi_f32(k, nw, doms, items, nitems, grid, j, stream);
-    case 2: return launch_batch_multi_f16(k, nw, doms, items, nitems, grid, j, stream);
+    case 0: return launch_batch_multi_f64(k, nw, def, doms, items, nitems, grid, j, stream);
+    case 1: return launch_batch_multi_f32(k, nw, def, doms, items, nitems, grid, j, stream);
+    case 2: return launch_batch_multi_f16(k, nw, def, doms, items, nitems, grid, j, stream);
   }
   return hipErrorInvalidValue;
 }
 
-int batch_multi_per_cu(int storage, int k, int nw) {
+int batch_multi_per_cu(int storage, int k, int nw, bool def) {
   switch (storage) {
-    case 0: return batch_multi_per_cu_f64(k, nw);
-    case 1: return batch_multi_per_cu_f32(k, nw);
-    case 2: return batch_multi_per_cu_f16(k, nw);
+    case 0: return batch_multi_per_cu_f64(k, nw, def);
+    case 1: return batch_multi_per_cu_f32(k, nw, def);
+    case 2: return batch_multi_per_cu_f16(k, nw, def);
   }
   return 0;
 }

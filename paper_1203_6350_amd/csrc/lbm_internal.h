@@ -101,19 +101,24 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
                         hipStream_t stream);
 // K = k steps (launch j of a tick) over the strip work items (int4: member,
 // first strip of the group, first row, rows), workgroups of nw waves.
-hipError_t launch_batch_multi(int storage, int k, int nw, const BatchDomain *doms,
+// def: every member has the default form's parameters (conserved rates 0,
+// n = m in the compute precision), which selects that form of the kernel.
+hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
                               const int4 *items, const int *nitems, int grid, int j,
                               hipStream_t stream);
-int batch_multi_per_cu(int storage, int k, int nw);
-hipError_t launch_batch_multi_f64(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                  const int *nitems, int grid, int j, hipStream_t stream);
-hipError_t launch_batch_multi_f32(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                  const int *nitems, int grid, int j, hipStream_t stream);
-hipError_t launch_batch_multi_f16(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                  const int *nitems, int grid, int j, hipStream_t stream);
-int batch_multi_per_cu_f64(int k, int nw);
-int batch_multi_per_cu_f32(int k, int nw);
-int batch_multi_per_cu_f16(int k, int nw);
+int batch_multi_per_cu(int storage, int k, int nw, bool def);
+hipError_t launch_batch_multi_f64(int k, int nw, bool def, const BatchDomain *doms,
+                                  const int4 *items, const int *nitems, int grid, int j,
+                                  hipStream_t stream);
+hipError_t launch_batch_multi_f32(int k, int nw, bool def, const BatchDomain *doms,
+                                  const int4 *items, const int *nitems, int grid, int j,
+                                  hipStream_t stream);
+hipError_t launch_batch_multi_f16(int k, int nw, bool def, const BatchDomain *doms,
+                                  const int4 *items, const int *nitems, int grid, int j,
+                                  hipStream_t stream);
+int batch_multi_per_cu_f64(int k, int nw, bool def);
+int batch_multi_per_cu_f32(int k, int nw, bool def);
+int batch_multi_per_cu_f16(int k, int nw, bool def);
 
 // Three-dimensional D3Q15 step (lbm3_kernels.hip): everything a kernel
 // needs in FP64, converted per launch to the compute precision.

@@ -427,7 +427,8 @@ __global__ __launch_bounds__(512) void step_multi_strip(
 // take at least (j + 1) K steps in it.
 // FP32 compute: registers for three waves per SIMD (the run-time variant
 // and rate switches would otherwise take it to two).
-template <typename S, int K>
+// DEF: every member has the default form's parameters (collide's DEF).
+template <typename S, int K, bool DEF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
 void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restrict__ items,
                        const int *__restrict__ nitems_dev, int j) {
@@ -462,7 +463,7 @@ void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restr
     p.dcf2 = C(d.dcf[2]);
 #define LBM_BATCH_RUN(VAR)                                                                   \
   {                                                                                          \
-    StripCtx<S, VAR, CHI_RUNTIME, K> c;                                                      \
+    StripCtx<S, VAR | (DEF ? V_DEF : 0), CHI_RUNTIME, K> c;                                  \
     strip_setup(c, (const S *)d.lat[par], (S *)d.lat[par ^ 1], d.nx, d.ny, d.pitch, d.ps,   \
                 strip, idle, it.z, nw, (const C *)d.chi_field, (const C *)d.chi_x,           \
                 (const C *)d.chi_y, d.chi_mode, scale, inv_scale, p);                        \
@@ -538,29 +539,42 @@ static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void
   return hipErrorInvalidValue;
 }
 
-template <typename S>
-hipError_t launch_batch_multi_storage(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                      const int *nitems, int grid, int j, hipStream_t s) {
+template <typename S, bool DEF>
+static hipError_t launch_batch_multi_t(int k, int nw, const BatchDomain *doms, const int4 *items,
+                                       const int *nitems, int grid, int j, hipStream_t s) {
   switch (k) {
-    case 2: batch_multi_strip<S, 2><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
-    case 3: batch_multi_strip<S, 3><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
-    case 4: batch_multi_strip<S, 4><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
+    case 2: batch_multi_strip<S, 2, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
+    case 3: batch_multi_strip<S, 3, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
+    case 4: batch_multi_strip<S, 4, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// Workgroups of nw waves of the batched multi-step kernel resident per CU.
 template <typename S>
-int batch_multi_per_cu(int k, int nw) {
+hipError_t launch_batch_multi_storage(int k, int nw, bool def, const BatchDomain *doms,
+                                      const int4 *items, const int *nitems, int grid, int j,
+                                      hipStream_t s) {
+  return def ? launch_batch_multi_t<S, true>(k, nw, doms, items, nitems, grid, j, s)
+             : launch_batch_multi_t<S, false>(k, nw, doms, items, nitems, grid, j, s);
+}
+
+template <typename S, bool DEF>
+static int batch_multi_per_cu_t(int k, int nw) {
   int per_cu = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (k) {
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 2>, 64 * nw, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 3>, 64 * nw, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 4>, 64 * nw, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 2, DEF>, 64 * nw, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 3, DEF>, 64 * nw, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 4, DEF>, 64 * nw, 0); break;
   }
   return e == hipSuccess ? per_cu : 0;
+}
+
+// Workgroups of nw waves of the batched multi-step kernel resident per CU.
+template <typename S>
+int batch_multi_per_cu(int k, int nw, bool def) {
+  return def ? batch_multi_per_cu_t<S, true>(k, nw) : batch_multi_per_cu_t<S, false>(k, nw);
 }
 
 // All variants, sponge forms and step counts of one storage type.

@@ -8,11 +8,12 @@ hipError_t launch_multi_f16(const StepConfig &c, int k, const void *src, void *d
   return launch_multi_storage<__half>(c, k, src, dst, stream);
 }
 
-hipError_t launch_batch_multi_f16(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                const int *nitems, int grid, int j, hipStream_t stream) {
-  return launch_batch_multi_storage<__half>(k, nw, doms, items, nitems, grid, j, stream);
+hipError_t launch_batch_multi_f16(int k, int nw, bool def, const BatchDomain *doms,
+                                const int4 *items, const int *nitems, int grid, int j,
+                                hipStream_t stream) {
+  return launch_batch_multi_storage<__half>(k, nw, def, doms, items, nitems, grid, j, stream);
 }
 
-int batch_multi_per_cu_f16(int k, int nw) { return batch_multi_per_cu<__half>(k, nw); }
+int batch_multi_per_cu_f16(int k, int nw, bool def) { return batch_multi_per_cu<__half>(k, nw, def); }
 
 }  // namespace lbm

@@ -8,11 +8,12 @@ hipError_t launch_multi_f64(const StepConfig &c, int k, const void *src, void *d
   return launch_multi_storage<double>(c, k, src, dst, stream);
 }
 
-hipError_t launch_batch_multi_f64(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                const int *nitems, int grid, int j, hipStream_t stream) {
-  return launch_batch_multi_storage<double>(k, nw, doms, items, nitems, grid, j, stream);
+hipError_t launch_batch_multi_f64(int k, int nw, bool def, const BatchDomain *doms,
+                                const int4 *items, const int *nitems, int grid, int j,
+                                hipStream_t stream) {
+  return launch_batch_multi_storage<double>(k, nw, def, doms, items, nitems, grid, j, stream);
 }
 
-int batch_multi_per_cu_f64(int k, int nw) { return batch_multi_per_cu<double>(k, nw); }
+int batch_multi_per_cu_f64(int k, int nw, bool def) { return batch_multi_per_cu<double>(k, nw, def); }
 
 }  // namespace lbm

@@ -561,6 +561,51 @@ def test_batch_equals_alone_bitwise(storage, tuning):
         lat.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_default_form_switch_bitwise(storage):
+    """The batched strip kernel has a form for members that all take the
+    paper's defaults (conserved rates 0, n = m) and a general one; adding a
+    member with other parameters switches the batch to the general form
+    (and back when it leaves), every member staying bit-identical to
+    stepping it alone."""
+    members = batch_members(9, 33, storage)
+    members[4]["s"] = (1.6,) * 9            # BGK rates
+    lats = [make_member(m, storage) for m in members]
+    odd = lbm.Lattice(members[6]["nx"], members[6]["ny"], rho=members[6]["rho"],
+                      ux=members[6]["ux"], uy=members[6]["uy"], storage=storage,
+                      variant=members[6]["variant"], s=members[6]["s"], ux_base=members[6]["ub"],
+                      f16_scale=1e-3, shift_n=0.3, shift_m=0.7)
+    odd.set_sponge(members[6]["chi"], members[6]["q"])
+    plain = [lat for k, lat in enumerate(lats) if k != 4]
+    b = lbm.Batch(plain)                    # all default: default form
+    b.set_min_items(0)
+    b.step(9)
+    b.set_members(lats)                     # a BGK member: general form
+    b.step(10)
+    b.set_members(lats + [odd])             # and one with n != m
+    b.step(6)
+    b.set_members(plain)                    # back to the default form
+    b.step(5)
+    b.sync()
+    steps = {k: (9 + 10 + 6 + 5 if k != 4 else 16) for k in range(len(members))}
+    for k, (m, lat) in enumerate(zip(members, lats)):
+        ref = make_member(m, storage)
+        ref.step(steps[k])
+        np.testing.assert_array_equal(lat.save_state(), ref.save_state())
+        ref.close()
+    ref = lbm.Lattice(members[6]["nx"], members[6]["ny"], rho=members[6]["rho"],
+                      ux=members[6]["ux"], uy=members[6]["uy"], storage=storage,
+                      variant=members[6]["variant"], s=members[6]["s"], ux_base=members[6]["ub"],
+                      f16_scale=1e-3, shift_n=0.3, shift_m=0.7)
+    ref.set_sponge(members[6]["chi"], members[6]["q"])
+    ref.step(6)
+    np.testing.assert_array_equal(odd.save_state(), ref.save_state())
+    ref.close()
+    b.close()
+    for lat in lats + [odd]:
+        lat.close()
+
+
 def test_batch_small_batch_switches_to_tiles_bitwise():
     """With the default threshold a batch of a few small members runs one-step
     tile launches, a large member list K-step launches; switching between
