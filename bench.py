@@ -34,10 +34,11 @@ PEAK_HBM_GBPS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
 # Arithmetic of one cell update (FMA = 2 flop) as the collision executes it
 # with the default parameters (conserved rates 0, n = m), counted on the
-# compiled loop of the four-step kernel: M g, the shifted conserved moments,
+# compiled loop of the four-step kernel (built as the library is, without
+# automatic contraction): M g, the shifted conserved moments,
 # the equilibrium deviations, relaxation and damping folded with D^-1, and
 # M^T; the one reciprocal of rho per cell and of 1 + n chi per row count once.
-FLOPS_PER_UPDATE = {"none": 118, "I": 148, "II": 146, "III": 140, "visc": 129}
+FLOPS_PER_UPDATE = {"none": 114, "I": 144, "II": 142, "III": 136, "visc": 126}
 METRIC = "D2Q9 MRT+sponge MLUPS & %HBM peak; batched-served vs plain MLUPS, p99 latency"
 CSRC = os.path.join(ROOT, "paper_1203_6350_amd", "csrc")
 # sources of the two step-kernel families: the K-step strip kernel and the

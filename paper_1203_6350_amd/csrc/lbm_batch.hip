@@ -83,6 +83,7 @@ __global__ __launch_bounds__(BX) void batch_step_kernel(
     p.dcf0 = C(d.dcf[0]);
     p.dcf1 = C(d.dcf[1]);
     p.dcf2 = C(d.dcf[2]);
+    set_relax_coeffs(p);
     switch (d.variant) {
       case V_I: collide<C, V_I>(g, chi, p); break;
       case V_II: collide<C, V_II>(g, chi, p); break;

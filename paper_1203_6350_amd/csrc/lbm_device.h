@@ -67,7 +67,25 @@ struct CollideParams {
   C n, m;          // shift parameters of rho* and j*
   C rho_b, ubx, uby;  // base state
   C dcf0, dcf1, dcf2; // q_ref - base: (rho^f - rho_b, j^f - j_b)
+  C sig[9], tau[9];   // rows k >= 3: (1 - s_k)/D_k and s_k/D_k (set_relax_coeffs)
 };
+
+// 1/D_k, D = diag(9, 6, 6, 36, 36, 12, 12, 4, 4): M's rows are orthogonal,
+// M^-1 = M^T D^-1.
+__host__ __device__ constexpr double dinv_of(int k) {
+  return k == 0 ? 1.0 / 9.0 : (k <= 2 ? 1.0 / 6.0 : (k <= 4 ? 1.0 / 36.0 : (k <= 6 ? 1.0 / 12.0 : 0.25)));
+}
+
+// The FP32 relaxation's per-row coefficients from the rates, in the compute
+// precision; host and device evaluate the same two IEEE operations, so
+// every construction of the parameters gives the same bits.
+template <typename C>
+__host__ __device__ inline void set_relax_coeffs(CollideParams<C> &p) {
+  for (int k = 0; k < 9; ++k) {
+    p.sig[k] = (C(1) - p.s[k]) * C(dinv_of(k));
+    p.tau[k] = p.s[k] * C(dinv_of(k));
+  }
+}
 
 template <typename C>
 __device__ __forceinline__ C fmaC(C a, C b, C c);
@@ -112,8 +130,8 @@ __device__ __forceinline__ void meq_delta(C dr, C djx, C djy, C rho_b, C ubx,
   out[0] = dr;
   out[1] = djx;
   out[2] = djy;
-  out[3] = C(3) * tr - C(2) * dr;
-  out[4] = dr - C(3) * tr;
+  out[3] = fmaC(C(3), tr, C(-2) * dr);
+  out[4] = fmaC(C(-3), tr, dr);
   out[5] = -djx;
   out[6] = -djy;
   out[7] = qxx - qyy;
@@ -153,10 +171,10 @@ __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p
   dm[0] = g[0] + sa + sd;
   dm[1] = ex + dx;
   dm[2] = ey + dy;
-  dm[3] = C(2) * sd - sa - C(4) * g[0];
-  dm[4] = C(4) * g[0] - C(2) * sa + sd;
-  dm[5] = dx - C(2) * ex;
-  dm[6] = dy - C(2) * ey;
+  dm[3] = fmaC(C(-4), g[0], fmaC(C(2), sd, -sa));
+  dm[4] = fmaC(C(4), g[0], fmaC(C(-2), sa, sd));
+  dm[5] = fmaC(C(-2), ex, dx);
+  dm[6] = fmaC(C(-2), ey, dy);
   dm[7] = ax - ay;
   dm[8] = (g[5] + g[7]) - (g[6] + g[8]);
 
@@ -186,8 +204,8 @@ __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p
   // ---- relaxation and damping, m' = dm + S o (dm^eq* - dm) + chi e
   // (Gamma = chi I), delivered as a_k = m'_k / D_k for the back-transform
   // M^-1 = M^T D^-1, D = diag(9, 6, 6, 36, 36, 12, 12, 4, 4).
-  constexpr double DINV[9] = {1.0 / 9.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 36.0, 1.0 / 36.0,
-                              1.0 / 12.0, 1.0 / 12.0, 0.25, 0.25};
+  constexpr double DINV[9] = {dinv_of(0), dinv_of(1), dinv_of(2), dinv_of(3), dinv_of(4),
+                              dinv_of(5), dinv_of(6), dinv_of(7), dinv_of(8)};
   C a[9];
   // conserved rows: a zero rate leaves the moment as it is
   {
@@ -270,21 +288,25 @@ __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p
     }
 #pragma unroll
     for (int k = 3; k < 9; ++k) {
-      C sk = p.s[k];
-      if (VAR == V_VISC) sk = fmaC(C(1) - sk, chi, sk);
-      a[k] = fmaC((C(1) - sk) * C(DINV[k]), dm[k], fmaC(sk * C(DINV[k]), meq[k], e[k]));
+      C sig = p.sig[k], tau = p.tau[k];
+      if (VAR == V_VISC) {
+        const C sk = fmaC(C(1) - p.s[k], chi, p.s[k]);
+        sig = (C(1) - sk) * C(DINV[k]);
+        tau = sk * C(DINV[k]);
+      }
+      a[k] = fmaC(sig, dm[k], fmaC(tau, meq[k], e[k]));
     }
   }
 
   // ---- g' = M^-1 dm' = M^T a
   const C a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4], a5 = a[5], a6 = a[6],
           a7 = a[7], a8 = a[8];
-  const C pa = a0 - a3 - C(2) * a4;   // shared by the axis directions
-  const C pd = a0 + C(2) * a3 + a4;   // shared by the diagonal directions
-  const C tx = a1 - C(2) * a5, ty = a2 - C(2) * a6;
+  const C pa = fmaC(C(-2), a4, a0 - a3);  // shared by the axis directions
+  const C pd = fmaC(C(2), a3, a0 + a4);   // shared by the diagonal directions
+  const C tx = fmaC(C(-2), a5, a1), ty = fmaC(C(-2), a6, a2);
   const C bx = a1 + a5, by = a2 + a6;
   const C pxa = pa + a7, pya = pa - a7;
-  g[0] = a0 - C(4) * a3 + C(4) * a4;
+  g[0] = fmaC(C(4), a4 - a3, a0);
   g[1] = pxa + tx;
   g[2] = pya + ty;
   g[3] = pxa - tx;

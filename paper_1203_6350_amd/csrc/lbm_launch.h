@@ -44,6 +44,7 @@ inline CollideParams<C> make_params(const StepConfig &c) {
   p.dcf0 = C(c.dcf[0]);
   p.dcf1 = C(c.dcf[1]);
   p.dcf2 = C(c.dcf[2]);
+  set_relax_coeffs(p);
   return p;
 }
 

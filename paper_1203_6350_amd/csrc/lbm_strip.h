@@ -461,6 +461,7 @@ void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restr
     p.dcf0 = C(d.dcf[0]);
     p.dcf1 = C(d.dcf[1]);
     p.dcf2 = C(d.dcf[2]);
+    set_relax_coeffs(p);
 #define LBM_BATCH_RUN(VAR)                                                                   \
   {                                                                                          \
     StripCtx<S, VAR | (DEF ? V_DEF : 0), CHI_RUNTIME, K> c;                                  \
