@@ -74,11 +74,14 @@ int lbm3_set_populations(lbm3_handle *h, const double *f);
  * may be NULL); synchronises. */
 int lbm3_moments(lbm3_handle *h, double *rho, double *ux, double *uy, double *uz);
 
-/* Workgroup size of the step (one cell per thread, a workgroup covers
- * consecutive cells of one row): 64..512 in steps of 64, default 256
- * (LBM_EINVAL otherwise). Every size gives bit-identical results. */
-int lbm3_set_tuning(lbm3_handle *h, int32_t block);
-int lbm3_get_tuning(lbm3_handle *h, int32_t *block);
+/* Launch shape of the step: kernel 0 = one cell per thread (a workgroup
+ * covers consecutive cells of one row); kernel 1 = two consecutive cells of
+ * a row per thread (nx even); block = threads per workgroup, 64..512 in
+ * steps of 64. Default: kernel 1 for FP16 storage when nx is even, else
+ * kernel 0; block 256. Every shape gives bit-identical results. LBM_EINVAL
+ * for an unavailable shape. */
+int lbm3_set_tuning(lbm3_handle *h, int32_t kernel, int32_t block);
+int lbm3_get_tuning(lbm3_handle *h, int32_t *kernel, int32_t *block);
 
 /* Number of steps taken since creation or the last lbm3_set_populations. */
 int lbm3_steps_done(lbm3_handle *h, int64_t *steps);

@@ -134,6 +134,122 @@ __global__ __launch_bounds__(512) void step3_kernel(
   for (int i = 0; i < 15; ++i) Store<S>::store(dst + i * ps + cell, g[i], L.inv_scale[i]);
 }
 
+// Row kernel: each thread owns V consecutive cells of one row and moves
+// every plane with one V-element access where the alignment allows it (the
+// five planes with c_x = 0; the ten x-shifted ones are read one element to
+// the left or right); the first and last thread of a row take the periodic
+// wrap with element loads. Threads are numbered over all rows
+// (nx % V == 0), so a wave covers 64 V consecutive cells. With V = 2 it
+// halves the FP16 accesses per byte.
+template <typename S, int V>
+struct RowV {
+  S v[V];
+};
+
+// One access of V * sizeof(S) bytes at element alignment.
+template <int B>
+struct RowWord;
+template <>
+struct RowWord<4> {
+  typedef unsigned int T __attribute__((aligned(2)));
+};
+template <>
+struct RowWord<8> {
+  typedef unsigned int T __attribute__((ext_vector_type(2), aligned(2)));
+};
+template <>
+struct RowWord<16> {
+  typedef unsigned int T __attribute__((ext_vector_type(4), aligned(2)));
+};
+
+template <typename S, int V>
+__device__ __forceinline__ void row_load(RowV<S, V> &d, const S *p) {
+  typedef typename RowWord<V * sizeof(S)>::T W;
+  const W w = *(const W *)p;
+  __builtin_memcpy(&d, &w, sizeof(d));
+}
+
+template <typename S, int VAR, int CHI, int V>
+__global__ __launch_bounds__(512) void step3_rows(
+    const S *__restrict__ src, S *__restrict__ dst, Lat3<S> L,
+    CollideParams3<typename Store<S>::C> p, const typename Store<S>::C *__restrict__ chi_field,
+    const typename Store<S>::C *__restrict__ chix, const typename Store<S>::C *__restrict__ chiy,
+    const typename Store<S>::C *__restrict__ chiz) {
+  typedef typename Store<S>::C C;
+  const int vpr = L.nx / V;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)vpr * L.ny * L.nz) return;
+  const int row = (int)(gid / vpr);  // y + ny z
+  const int x0 = (int)(gid - (int64_t)row * vpr) * V;
+  const int z = row / L.ny, y = row - z * L.ny;
+  const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
+  const int64_t sz0 = (int64_t)z * L.slice, szm = (int64_t)zm * L.slice,
+                szp = (int64_t)zp * L.slice;
+  const int64_t ry0 = (int64_t)y * L.pitch, rym = (int64_t)ym * L.pitch,
+                ryp = (int64_t)yp * L.pitch;
+  const int64_t ps = L.ps;
+  // source row of each plane (pull g_i(x) <- g'_i(x - c_i)), before the x shift
+  const int64_t base[15] = {sz0 + ry0, sz0 + ry0, sz0 + ry0, sz0 + rym, sz0 + ryp,
+                            szm + ry0, szp + ry0, szm + rym, szm + rym, szm + ryp,
+                            szm + ryp, szp + rym, szp + rym, szp + ryp, szp + ryp};
+  RowV<S, V> in[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) {
+    const S *rowp = src + i * ps + base[i];
+    if (c3x(i) == 0) {
+      row_load(in[i], rowp + x0);
+    } else if (c3x(i) > 0) {  // pull from x - 1
+      if (x0 > 0) {
+        row_load(in[i], rowp + x0 - 1);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) in[i].v[v] = rowp[v == 0 ? L.nx - 1 : v - 1];
+      }
+    } else {  // pull from x + 1
+      if (x0 + V < L.nx) {
+        row_load(in[i], rowp + x0 + 1);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) in[i].v[v] = rowp[x0 + v + 1 == L.nx ? 0 : x0 + v + 1];
+      }
+    }
+  }
+  const int64_t cell0 = sz0 + ry0 + x0;
+  RowV<S, V> out[15];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    C g[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) g[i] = Store<S>::load(&in[i].v[v], L.scale[i]);
+    const C chi = chi3_at<C, CHI>(chi_field, chix, chiy, chiz, cell0 + v, x0 + v, y, z);
+    collide3<C, VAR>(g, chi, p);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Store<S>::store(&out[i].v[v], g[i], L.inv_scale[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 15; ++i) __builtin_memcpy(dst + i * ps + cell0, &out[i], sizeof(out[i]));
+}
+
+template <typename S, int VAR, int CHI, int V>
+static hipError_t launch_rows3(const Step3Config &c, const Lat3<S> &L,
+                               const CollideParams3<typename Store<S>::C> &p, const void *src,
+                               void *dst, hipStream_t stream) {
+  typedef typename Store<S>::C C;
+  if constexpr (V < 2) {
+    return hipErrorInvalidValue;
+  } else {
+    if (c.nx % V) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(c.nx / V) * c.ny * c.nz;
+    const int64_t blocks = (n + c.block - 1) / c.block;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    step3_rows<S, VAR, CHI, V><<<dim3((unsigned)blocks), dim3(c.block), 0, stream>>>(
+        (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
+        (const C *)c.chi_y, (const C *)c.chi_z);
+    return hipGetLastError();
+  }
+}
+
 template <typename S, int VAR, int CHI>
 static hipError_t launch_step3_t(const Step3Config &c, const void *src, void *dst,
                                  hipStream_t stream) {
@@ -142,6 +258,8 @@ static hipError_t launch_step3_t(const Step3Config &c, const void *src, void *ds
   const CollideParams3<C> p = make_params3<C>(c);
   const int bx = c.block;
   if (bx < 64 || bx > 512 || bx % 64) return hipErrorInvalidValue;
+  if (c.kernel == 1) return launch_rows3<S, VAR, CHI, 2>(c, L, p, src, dst, stream);
+  if (c.kernel != 0) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t)((c.nx + bx - 1) / bx) * c.ny * c.nz;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   step3_kernel<S, VAR, CHI><<<dim3((unsigned)blocks), dim3(bx), 0, stream>>>(

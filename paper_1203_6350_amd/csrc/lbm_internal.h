@@ -134,6 +134,7 @@ struct Step3Config {
   double f16_scale;
   const void *chi_field; // [nz][ny][pitch] compute type
   const void *chi_x, *chi_y, *chi_z;
+  int kernel;            // 0: one cell per thread; 1: two cells of a row per thread (nx even)
   int block;             // threads per workgroup, 64..512, a multiple of 64
 };
 hipError_t launch_step3(const Step3Config &c, const void *src, void *dst, hipStream_t stream);

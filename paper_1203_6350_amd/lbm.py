@@ -153,8 +153,8 @@ def load(path: str | None = None):
         "lbm3_set_populations": [_H, _DP],
         "lbm3_moments": [_H, _DP, _DP, _DP, _DP],
         "lbm3_steps_done": [_H, ctypes.POINTER(i64)],
-        "lbm3_set_tuning": [_H, i32],
-        "lbm3_get_tuning": [_H, ctypes.POINTER(i32)],
+        "lbm3_set_tuning": [_H, i32, i32],
+        "lbm3_get_tuning": [_H, ctypes.POINTER(i32), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -711,14 +711,14 @@ def lbm3_steps_done(h):
     return v.value
 
 
-def lbm3_set_tuning(h, block=256):
-    _check(load().lbm3_set_tuning(h, int(block)))
+def lbm3_set_tuning(h, kernel=0, block=256):
+    _check(load().lbm3_set_tuning(h, int(kernel), int(block)))
 
 
 def lbm3_get_tuning(h):
-    b = ctypes.c_int32()
-    _check(load().lbm3_get_tuning(h, ctypes.byref(b)))
-    return {"block": b.value}
+    k, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lbm3_get_tuning(h, ctypes.byref(k), ctypes.byref(b)))
+    return {"kernel": k.value, "block": b.value}
 
 
 def lbm3_destroy(h):
@@ -758,8 +758,8 @@ class Lattice3:
     def steps_done(self):
         return lbm3_steps_done(self.h)
 
-    def set_tuning(self, block=256):
-        lbm3_set_tuning(self.h, block)
+    def set_tuning(self, kernel=0, block=256):
+        lbm3_set_tuning(self.h, kernel, block)
 
     def tuning(self):
         return lbm3_get_tuning(self.h)

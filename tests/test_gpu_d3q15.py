@@ -298,34 +298,44 @@ def test_full_size_cube_sampled_against_oracle():
 # ------------------------------------------------------------------ launch shapes
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("nx,ny,nz", [(16, 5, 3), (40, 9, 7), (8, 1, 2), (600, 3, 2)])
-def test_every_block_size_bitwise_identical(storage, nx, ny, nz):
-    """Every workgroup size gives the same bits (rows shorter and longer than
-    a workgroup, ragged tails); FP64 against the oracle."""
-    say("case: D3Q15 blocks", storage, nx, ny, nz)
+@pytest.mark.parametrize("nx,ny,nz", [(16, 5, 3), (40, 9, 7), (8, 1, 2), (600, 3, 2), (21, 4, 3), (2, 3, 2)])
+def test_every_launch_shape_bitwise_identical(storage, nx, ny, nz):
+    """One and two cells per thread with every workgroup size: the same bits
+    (rows shorter and longer than a workgroup, ragged tails, the periodic
+    wrap at row ends); FP64 against the oracle."""
+    say("case: D3Q15 shapes", storage, nx, ny, nz)
     F = noisy_fields(nx, ny, nz, 81 + nx)
     chi = wl.sponge_3d(*profiles(nx, ny, nz, 0.3))
+    shapes = [(0, b) for b in (64, 128, 256, 320, 512)]
+    shapes += [(1, b) for b in (64, 256, 512) if nx % 2 == 0]
     states = []
-    for b in (64, 128, 256, 320, 512):
+    for k, b in shapes:
         lat = lbm.Lattice3(nx, ny, nz, rho=F[0], ux=F[1], uy=F[2], uz=F[3], storage=storage,
                            variant="II", s=S_MIX, f16_scale=1e-3, **UB)
         lat.set_sponge(chi, QREF)
-        lat.set_tuning(block=b)
-        assert lat.tuning() == {"block": b}
+        lat.set_tuning(kernel=k, block=b)
+        assert lat.tuning() == {"kernel": k, "block": b}
         lat.step(7)
-        states.append((b, lat.populations()))
+        states.append(((k, b), lat.populations()))
         lat.close()
-    for b, st in states[1:]:
-        assert np.array_equal(st, states[0][1]), b
+    for t, st in states[1:]:
+        assert np.array_equal(st, states[0][1]), t
     if storage == "f64":
         ref = o3.step(o3.feq_field(*F), 7, s=S_MIX, chi=chi, qref=QREF, variant="II")
         assert rel_max(states[-1][1], ref) <= 1e-12
 
 
-def test_bad_block_size_rejected():
-    lat = lbm.Lattice3(12, 4, 4, storage="f16")
-    assert lat.tuning() == {"block": 256}
-    for b in (0, 32, 96, 1024):
+def test_bad_launch_shape_rejected():
+    lat = lbm.Lattice3(13, 4, 4, storage="f16")
+    assert lat.tuning() == {"kernel": 0, "block": 256}     # odd nx
+    for k, b in ((0, 0), (0, 32), (0, 96), (0, 1024), (2, 256), (1, 256)):
         with pytest.raises(lbm.LbmError):
-            lat.set_tuning(block=b)
+            lat.set_tuning(kernel=k, block=b)
+    lat.close()
+    lat = lbm.Lattice3(12, 4, 4, storage="f16")
+    assert lat.tuning() == {"kernel": 1, "block": 256}
+    lat.close()
+    lat = lbm.Lattice3(12, 4, 4, storage="f32")
+    assert lat.tuning() == {"kernel": 0, "block": 256}
+    lat.set_tuning(kernel=1, block=128)
     lat.close()
