@@ -413,8 +413,9 @@ int lbm_step(lbm_handle *h, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   int64_t k = 0;
   const int per = h->cfg.kernel;  // time steps per launch of the multi-step kernel
-  // a per-cell reference state or a channel runs in the one-step kernel only
-  if (per >= lbm::KERNEL_MULTI_MIN && !h->qf && !h->channel) {
+  // a channel, a running-mean reference state, or a per-cell one with
+  // parameters other than the default form run in the one-step kernel only
+  if (per >= lbm::KERNEL_MULTI_MIN && lbm::multi_step_supports(h->cfg)) {
     while (n - k >= 2) {
       const int m = n - k >= per ? per : (int)(n - k);
       hipError_t e = lbm::launch_multi_steps(h->cfg, m, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
@@ -593,9 +594,10 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
     for (int nt = 0; nt < 2; ++nt)
       for (int b : blocks) cands.push_back(lbm_tuning{1, b, nt, 0});
   const int rows[4] = {0, 8, 16, 32};
-  for (int kk = lbm::KERNEL_MULTI_MIN; kk <= lbm::KERNEL_MULTI_MAX; ++kk)
-    for (int b : blocks)
-      for (int r : rows) cands.push_back(lbm_tuning{kk, b, 0, r});
+  if (lbm::multi_step_supports(h->cfg))  // lbm_step would not run them otherwise
+    for (int kk = lbm::KERNEL_MULTI_MIN; kk <= lbm::KERNEL_MULTI_MAX; ++kk)
+      for (int b : blocks)
+        for (int r : rows) cands.push_back(lbm_tuning{kk, b, 0, r});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   hipError_t e = hipEventCreate(&e1);

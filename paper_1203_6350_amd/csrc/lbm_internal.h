@@ -41,6 +41,20 @@ struct StepConfig {
 };
 
 enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MAX = 4 };
+
+// The multi-step strip kernels take this configuration: no channel, and a
+// per-cell reference state only when it is fixed in time and the collision
+// has its default form (conserved rates 0, n = m in the compute precision);
+// the undamped and viscosity-ramp variants ignore the reference state.
+inline bool multi_step_supports(const StepConfig &c) {
+  if (c.channel) return false;
+  if (!c.qfield || c.variant == 0 || c.variant == 4) return true;
+  if (c.qalpha != 0.0) return false;
+  if (c.storage == 0)
+    return c.s[0] == 0.0 && c.s[1] == 0.0 && c.s[2] == 0.0 && c.n == c.m;
+  return (float)c.s[0] == 0.0f && (float)c.s[1] == 0.0f && (float)c.s[2] == 0.0f &&
+         (float)c.n == (float)c.m;
+}
 // k = 2..4 time steps in one launch (src at t -> dst at t + k).
 hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void *dst,
                               hipStream_t stream);

@@ -52,8 +52,12 @@ constexpr int CHI_RUNTIME = 4;
 // V_DEF set: in the compute precision the launch's conserved rates s_0,
 // s_1, s_2 are all 0 and its shift parameters n and m are equal (collide's
 // DEF).
+// V_QF: a per-cell reference state (fixed in time) replaces the uniform
+// q_ref: three planes of the reference's conserved-moment deviations, read
+// per row like a sponge field (only with V_DEF and the damped variants).
 constexpr int V_MASK = 7;
 constexpr int V_DEF = 8;
+constexpr int V_QF = 16;
 
 template <int K>
 constexpr int strip_width() {
@@ -124,6 +128,7 @@ struct StripState {
   C a013[3][3];         // input rows: populations 0, 1, 3
   C a256[3][3];         // input rows: populations 2, 5, 6
   C craw[6];            // sponge input (chi_raw) of the rows, slot q % 6
+  C qraw[6][3];         // reference-state deviations of the rows (V_QF), slot q % 6
   C b013[K - 1][2][3];  // results of steps 1..K-1: populations 0, 1, 3
   C b256[K - 1][3][3];  // results of steps 1..K-1: populations 2, 5, 6
 };
@@ -146,6 +151,10 @@ struct StripCtx {
   C scale[9], inv_scale[9];
   CollideParams<C> p;
   C mref[9];
+  const C *qf;         // V_QF: [3][qps] reference-state deviations, rows of `pitch`
+  int64_t qps;
+
+  static constexpr bool QF = (VAR & V_QF) != 0;
 
   __device__ __forceinline__ int wrap_row(int r) const {
     r %= ny;
@@ -199,6 +208,34 @@ struct StripCtx {
     if (m == CHI_ZERO) return C(0);
     if (m == CHI_FIELD) return chi_field[(int64_t)r * pitch + col];
     return chiy[r];
+  }
+  // Per-row cell inputs of row r into ring slot Q: the sponge input and,
+  // with a reference field, the cell's reference-state deviations.
+  template <int Q>
+  __device__ __forceinline__ void row_inputs(StripState<C, K> &st, int r) const {
+    st.craw[md<6>(Q)] = chi_raw(r);
+    if constexpr (QF) {
+      const int64_t cell = (int64_t)r * pitch + col;
+      st.qraw[md<6>(Q)][0] = qf[cell];
+      st.qraw[md<6>(Q)][1] = qf[qps + cell];
+      st.qraw[md<6>(Q)][2] = qf[2 * qps + cell];
+    }
+  }
+  // The collision of a cell of the row in ring slot Q.
+  template <int Q>
+  __device__ __forceinline__ void collide_at(const StripState<C, K> &st, C g[9]) const {
+    const C chi = chi_of(st.craw[md<6>(Q)]);
+    if constexpr (QF) {
+      CollideParams<C> pc = p;
+      pc.dcf0 = st.qraw[md<6>(Q)][0];
+      pc.dcf1 = st.qraw[md<6>(Q)][1];
+      pc.dcf2 = st.qraw[md<6>(Q)][2];
+      C mr[9];
+      if ((VAR & V_MASK) == V_I || (VAR & V_MASK) == V_II) ref_moments(pc, mr);
+      collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(g, chi, pc, mr);
+    } else {
+      collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(g, chi, p, mref);
+    }
   }
   __device__ __forceinline__ C chi_of(C raw) const {
     const int m = mode();
@@ -254,11 +291,10 @@ struct StripCtx {
     }
     // row a - 2's {2, 5, 6} are consumed: its slot takes row a + 1's
     if (left > 3) load_256<P + 1>(st, r_next);
-    const C chi1 = chi_of(st.craw[md<6>(P - 1)]);
-    // the sponge input of row a + 1 is read after this use, so waiting for
-    // it does not hold up this row
-    if (left > 2) st.craw[md<6>(P + 1)] = chi_raw(r_next);
-    collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(g, chi1, p, mref);
+    // the cell inputs of row a + 1 go to another ring slot than row a - 1's,
+    // and are first needed in the next iteration
+    if (left > 2) row_inputs<P + 1>(st, r_next);
+    collide_at<P - 1>(st, g);
     chain<P, J, 2>(st, g, a);
   }
 
@@ -275,7 +311,7 @@ struct StripCtx {
       pull<C>(st.b256[j - 2][md<3>(P - j - 1)], st.b013[j - 2][md<2>(P - j)], g[4], g[7], g[8],
               o);
       keep<j - 1, P - (j - 1)>(st, g);
-      collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(o, chi_of(st.craw[md<6>(P - j)]), p, mref);
+      collide_at<P - j>(st, o);
       if constexpr (j == K) {
         if (store_lane) {
 #pragma unroll
@@ -299,9 +335,13 @@ __device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S
                                             const typename Store<S>::C *chiy, int chi_mode,
                                             const typename Store<S>::C scale[9],
                                             const typename Store<S>::C inv_scale[9],
-                                            const CollideParams<typename Store<S>::C> &p) {
+                                            const CollideParams<typename Store<S>::C> &p,
+                                            const typename Store<S>::C *qf = nullptr,
+                                            int64_t qps = 0) {
   typedef typename Store<S>::C C;
   constexpr int W = strip_width<K>();
+  c.qf = qf;
+  c.qps = qps;
   const int lane = threadIdx.x & 63;
   c.src = src;
   c.dst = dst;
@@ -329,7 +369,8 @@ __device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S
     c.inv_scale[i] = inv_scale[i];
   }
   c.p = p;
-  if ((VAR & V_MASK) == V_I || (VAR & V_MASK) == V_II) ref_moments(p, c.mref);
+  if (!StripCtx<S, VAR, CHI, K>::QF && ((VAR & V_MASK) == V_I || (VAR & V_MASK) == V_II))
+    ref_moments(p, c.mref);
 }
 
 // The row loop of one strip over R output rows from Y0 on.
@@ -346,12 +387,12 @@ __device__ __forceinline__ void strip_run(const StripCtx<S, VAR, CHI, K> &c, int
   r = next(r);
   c.template load_256<1>(st, r);
   c.template load_013<1>(st, r);
-  st.craw[1] = c.chi_raw(r);
+  c.template row_inputs<1>(st, r);
   r = next(r);
   c.template load_478<2>(st, r);
   c.template load_013<2>(st, r);
   c.template load_256<2>(st, r);
-  st.craw[2] = c.chi_raw(r);
+  c.template row_inputs<2>(st, r);
   c.template load_478<3>(st, next(r));
   // Iterations q = 2 .. R + 2K - 1 at input rows a = Y0 - K + q. Step j runs
   // from q = 2j on: q = 2, 3 run step 1, q = 4, 5 steps 1-2, q = 6, 7 steps
@@ -401,8 +442,8 @@ __global__ __launch_bounds__(512) void step_multi_strip(
     CollideParams<typename Store<S>::C> p,
     const typename Store<S>::C *__restrict__ chi_field,
     const typename Store<S>::C *__restrict__ chix,
-    const typename Store<S>::C *__restrict__ chiy, int rows_per_chunk,
-    int nstrips, int ngroups, int wg_per_xcd, int nwg) {
+    const typename Store<S>::C *__restrict__ chiy, const typename Store<S>::C *__restrict__ qf,
+    int64_t qps, int rows_per_chunk, int nstrips, int ngroups, int wg_per_xcd, int nwg) {
   // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
   // contiguous range of work (a band of chunk rows) so neighbouring strips
   // and chunks share an L2
@@ -416,7 +457,7 @@ __global__ __launch_bounds__(512) void step_multi_strip(
   const int Y0 = chunk * rows_per_chunk;
   StripCtx<S, VAR, CHI, K> c;
   strip_setup(c, src, dst, L.nx, L.ny, L.pitch, L.ps, strip, idle, Y0, nw, chi_field, chix, chiy,
-              CHI, L.scale, L.inv_scale, p);
+              CHI, L.scale, L.inv_scale, p, qf, qps);
   strip_run(c, min(rows_per_chunk, L.ny - Y0));
 }
 
@@ -525,7 +566,8 @@ static hipError_t launch_multi_t(const StepConfig &c, const void *src, void *dst
   if (8 * per_xcd > 0x7fffffff) return hipErrorInvalidValue;
   step_multi_strip<S, VAR, CHI, K><<<dim3((unsigned)(8 * per_xcd)), dim3(64 * nw), 0, stream>>>(
       (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
-      (const C *)c.chi_y, rows, nstrips, ngroups, (int)per_xcd, (int)nwg);
+      (const C *)c.chi_y, (const C *)c.qfield, c.qps, rows, nstrips, ngroups, (int)per_xcd,
+      (int)nwg);
   return hipGetLastError();
 }
 
@@ -593,6 +635,15 @@ hipError_t launch_multi_storage(const StepConfig &c, int k, const void *src, voi
   typedef typename Store<S>::C C;
   const bool def = C(c.s[0]) == C(0) && C(c.s[1]) == C(0) && C(c.s[2]) == C(0) &&
                    C(c.n) == C(c.m);
+  if (c.qfield && (c.variant == V_I || c.variant == V_II || c.variant == V_III)) {
+    // a per-cell reference state: the default form only (multi_step_supports)
+    if (!def) return hipErrorInvalidValue;
+    switch (c.variant) {
+      case V_I: { LBM_CHI(V_I | V_DEF | V_QF) }
+      case V_II: { LBM_CHI(V_II | V_DEF | V_QF) }
+      case V_III: { LBM_CHI(V_III | V_DEF | V_QF) }
+    }
+  }
   if (def) {
     switch (c.variant) {
       case V_NONE: { LBM_CHI(V_NONE | V_DEF) }

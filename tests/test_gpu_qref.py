@@ -166,3 +166,73 @@ def test_reference_field_round_trip_and_batch_refusal():
     with pytest.raises(lbm.LbmError):
         lat.set_qref_average(0.1)
     lat.close()
+
+
+STRIP_TUNINGS = [dict(kernel=2, block=128, rows=5), dict(kernel=3, block=256, rows=0),
+                 dict(kernel=4, block=64, rows=7), dict(kernel=4, block=128, rows=0)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("variant", ["II", "I", "III", "none", "visc"])
+def test_fixed_reference_field_in_strip_kernels_bitwise(storage, variant):
+    """A per-cell reference state fixed in time runs in the multi-step strip
+    kernels (the row's field values travel with its sponge input): every
+    strip shape gives the bits of the one-cell-per-thread kernel, for every
+    sponge form, with whole launches and a remainder (11 steps); FP64 against
+    the oracle."""
+    nx, ny, T = 133, 37, 11
+    say("case: fixed reference field in strips", storage, variant)
+    rho, ux, uy, chi, q = case(nx, ny, 40 + len(variant))
+    if variant == "I":
+        chi = np.minimum(chi, 0.1)
+    if variant == "visc":
+        chi = np.minimum(chi, 1.0)
+    g = np.random.default_rng(9)
+    cx = np.minimum(g.uniform(0, 0.3, nx) * (g.uniform(size=nx) < 0.4), chi.max())
+    cy = np.minimum(g.uniform(0, 0.3, ny) * (g.uniform(size=ny) < 0.4), chi.max())
+    for form in ("field", "max", "sum"):
+        states = []
+        for t in [dict(kernel=0, block=256)] + STRIP_TUNINGS:
+            lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant=variant,
+                              ux_base=0.04, f16_scale=1e-3)
+            if form == "field":
+                lat.set_sponge(chi, (1.0, 0.04, 0.0))
+            else:
+                lat.set_sponge_separable(cx, cy, form, (1.0, 0.04, 0.0))
+            lat.set_qref_field(*q)
+            lat.set_tuning(**t)
+            lat.step(T)
+            states.append(lat.save_state())
+            if storage == "f64" and form == "field" and t == STRIP_TUNINGS[-1]:
+                got = lat.populations()
+            lat.close()
+        for t, st in zip(STRIP_TUNINGS, states[1:]):
+            assert (st == states[0]).all(), (form, t)
+    if storage == "f64":
+        ref, _ = oracle.step_avg(oracle.feq_field(rho, ux, uy), conserved(q), T, alpha=0.0,
+                                 chi=chi, variant=variant)
+        assert rel_max(got, ref) <= 1e-12
+
+
+def test_reference_field_other_parameters_use_one_step_kernel():
+    """Rates or shifts other than the default form, and a running mean,
+    keep the reference field in the one-cell kernel: still the oracle's
+    result (FP64) under a strip tuning."""
+    nx, ny, T = 70, 33, 9
+    rho, ux, uy, chi, q = case(nx, ny, 61)
+    S = (0.0, 0.3, 0.0, 1.2, 1.3, 1.4, 1.5, 1.6, 1.7)
+    for kw, alpha in ((dict(s=S), 0.0), (dict(shift_n=0.3, shift_m=0.7), 0.0), ({}, 0.05)):
+        lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage="f64", variant="II",
+                          ux_base=0.04, **kw)
+        lat.set_sponge(chi, (1.0, 0.04, 0.0))
+        lat.set_qref_field(*q)
+        if alpha:
+            lat.set_qref_average(alpha)
+        lat.set_tuning(kernel=4, block=128, rows=0)
+        lat.step(T)
+        got = lat.populations()
+        lat.close()
+        ref, _ = oracle.step_avg(oracle.feq_field(rho, ux, uy), conserved(q), T, alpha=alpha,
+                                 chi=chi, variant="II", s=kw.get("s", oracle.S_MRT_DEFAULT),
+                                 n=kw.get("shift_n", 0.5), m=kw.get("shift_m", 0.5))
+        assert rel_max(got, ref) <= 1e-12, kw
