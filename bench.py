@@ -401,11 +401,12 @@ def cpu_baseline(spec, fields, steps, wl=None):
 
 
 def qref_leg(lbm, wl, torch, n=4096, steps=400, warmup=20, alpha=1e-3):
-    """The headline workload with a per-cell reference state: fixed in time
-    (in the one-cell kernel, and in the autotuned strip kernels, where the
-    field rows travel with the sponge input: 72 + 12 B per cell per launch),
-    and following the flow as a running mean of rate alpha (one-cell kernel
-    only, the field read and written every step: 72 + 24 B per update)."""
+    """The headline workload with a per-cell reference state, fixed in time
+    or following the flow as a running mean of rate alpha, each in the
+    one-cell kernel and in the autotuned strip kernels (where the field rows
+    travel with the sponge input). Bytes per cell per launch (FP32): 72 + 12
+    (fixed) or 72 + 24 (running mean: read, and written to the second
+    buffer); one launch is K steps in the strips."""
     sp = wl.large_c2(variant="II", storage="f32", n=n)
     rho, ux, uy = sp.fields()
     stream = torch.cuda.current_stream()
@@ -416,7 +417,8 @@ def qref_leg(lbm, wl, torch, n=4096, steps=400, warmup=20, alpha=1e-3):
     lat.set_qref_field(rho, ux, uy)
     out = {}
     for name, a, tune in (("alpha=0,one_cell", 0.0, "one"), ("alpha=0", 0.0, "auto"),
-                          ("alpha=%g" % alpha, alpha, "one")):
+                          ("alpha=%g,one_cell" % alpha, alpha, "one"),
+                          ("alpha=%g" % alpha, alpha, "auto")):
         lat.set_qref_average(a)
         if tune == "one":
             lat.set_tuning(kernel=0, block=256)

@@ -75,6 +75,7 @@ struct lbm_handle {
   void *chi_x = nullptr;      // compute type [nx]
   void *chi_y = nullptr;      // compute type [ny]
   void *qf = nullptr;         // compute type [3][qps]: per-cell reference, or NULL
+  void *qf2 = nullptr;        // second buffer for the strip kernels' running mean
   int64_t qps = 0;
   double qalpha = 0.0;        // running-mean rate of the reference
   int channel = 0;            // line source at x = 0 (Sec. 4.2)
@@ -142,6 +143,7 @@ void fill_cfg(lbm_handle *h) {
   s.chi_x = h->chi_x;
   s.chi_y = h->chi_y;
   s.qfield = h->qf;
+  s.qfield_out = h->qf2;
   s.qps = h->qps;
   s.qalpha = h->qf ? h->qalpha : 0.0;
   s.channel = h->channel;
@@ -328,6 +330,17 @@ int create_common(const lbm_config *cfg, const double *rho, const double *ux,
 
 }  // namespace
 
+namespace {
+// The second reference-field buffer of the strip kernels' running mean.
+int ensure_qf2(lbm_handle *h) {
+  if (h->qf2) return LBM_OK;
+  const size_t eb = h->user.storage == LBM_STORAGE_F64 ? 8 : 4;
+  HIP_TRY(hipMallocAsync(&h->qf2, (size_t)(3 * h->qps) * eb, h->stream), "hipMallocAsync(reference)");
+  h->cfg.qfield_out = h->qf2;
+  return LBM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int lbm_required_bytes(const lbm_config *cfg, size_t *bytes) {
@@ -416,6 +429,13 @@ int lbm_step(lbm_handle *h, int64_t n) {
   // a channel, a running-mean reference state, or a per-cell one with
   // parameters other than the default form run in the one-step kernel only
   if (per >= lbm::KERNEL_MULTI_MIN && lbm::multi_step_supports(h->cfg)) {
+    // a running-mean reference: each launch writes the updated field to the
+    // second buffer, which then becomes the current one
+    const bool qa = h->qf && h->qalpha != 0.0;
+    if (qa && n - k >= 2) {
+      int rc = ensure_qf2(h);
+      if (rc) return rc;
+    }
     while (n - k >= 2) {
       const int m = n - k >= per ? per : (int)(n - k);
       hipError_t e = lbm::launch_multi_steps(h->cfg, m, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
@@ -423,6 +443,11 @@ int lbm_step(lbm_handle *h, int64_t n) {
       h->cur = 1 - h->cur;
       h->steps += m;
       k += m;
+      if (qa) {
+        std::swap(h->qf, h->qf2);
+        h->cfg.qfield = h->qf;
+        h->cfg.qfield_out = h->qf2;
+      }
     }
   }
   for (; k < n; ++k) {
@@ -605,6 +630,25 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
     (void)hipEventDestroy(e0);
     return hip_fail(e, "hipEventCreate");
   }
+  // the running mean would advance during the timing: keep a copy
+  void *qf_keep = nullptr;
+  const size_t qf_bytes = h->qf ? (size_t)(3 * h->qps) * (h->user.storage == LBM_STORAGE_F64 ? 8 : 4) : 0;
+  if (h->qf && h->qalpha != 0.0) {
+    int rc = ensure_qf2(h);
+    if (rc) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    e = hipMallocAsync(&qf_keep, qf_bytes, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(qf_keep, h->qf, qf_bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) {
+      if (qf_keep) (void)hipFreeAsync(qf_keep, h->stream);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return hip_fail(e, "autotune reference copy");
+    }
+  }
   const lbm::StepConfig saved = h->cfg;
   double best_t = 1e300;
   lbm_tuning best_c = cands[0];
@@ -636,6 +680,11 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->cfg = saved;
+  if (qf_keep) {
+    const hipError_t e2 = hipMemcpyAsync(h->qf, qf_keep, qf_bytes, hipMemcpyDeviceToDevice, h->stream);
+    (void)hipFreeAsync(qf_keep, h->stream);
+    if (e == hipSuccess) e = e2;
+  }
   if (e != hipSuccess) return hip_fail(e, "autotune");
   h->cfg.kernel = best_c.kernel;
   h->cfg.block = best_c.block;
@@ -650,6 +699,7 @@ void lbm_destroy(lbm_handle *h) {
   if (!h) return;
   free_sponge(h);
   if (h->qf) (void)hipFreeAsync(h->qf, h->stream);
+  if (h->qf2) (void)hipFreeAsync(h->qf2, h->stream);
   if (h->diag_partials) (void)hipFreeAsync(h->diag_partials, h->stream);
   if (h->diag_out) (void)hipFreeAsync(h->diag_out, h->stream);
   if (h->own_lat) {
@@ -666,7 +716,8 @@ int lbm_set_qref_field(lbm_handle *h, const double *rho_f, const double *ux_f,
   if (!rho_f && !ux_f && !uy_f) {
     HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     if (h->qf) (void)hipFreeAsync(h->qf, h->stream);
-    h->qf = nullptr;
+    if (h->qf2) (void)hipFreeAsync(h->qf2, h->stream);
+    h->qf = h->qf2 = nullptr;
     h->qalpha = 0.0;
     fill_cfg(h);
     return LBM_OK;
@@ -693,7 +744,8 @@ int lbm_set_qref_field(lbm_handle *h, const double *rho_f, const double *ux_f,
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   if (h->qf && h->qps != qps) {
     (void)hipFreeAsync(h->qf, h->stream);
-    h->qf = nullptr;
+    if (h->qf2) (void)hipFreeAsync(h->qf2, h->stream);
+    h->qf = h->qf2 = nullptr;
   }
   h->qps = qps;
   int rc = upload_compute(h, host.data(), host.size(), &h->qf);

@@ -32,6 +32,7 @@ struct StepConfig {
   // per-cell reference state: three planes [3][qps] of (d rho^f, d j^f_x,
   // d j^f_y), each [ny][pitch], compute type; NULL: uniform dcf above
   void *qfield;
+  void *qfield_out;      // second field buffer of the strip kernels' running mean
   int64_t qps;
   double qalpha;         // running-mean rate of the reference (0: fixed)
   // channel in x (line source at x = 0, optional outflow at x = nx - 1)
@@ -43,13 +44,16 @@ struct StepConfig {
 enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MAX = 4 };
 
 // The multi-step strip kernels take this configuration: no channel, and a
-// per-cell reference state only when it is fixed in time and the collision
-// has its default form (conserved rates 0, n = m in the compute precision);
-// the undamped and viscosity-ramp variants ignore the reference state.
+// per-cell reference state only when the collision has its default form
+// (conserved rates 0, n = m in the compute precision). A fixed reference is
+// ignored by the undamped and viscosity-ramp variants; a running mean (which
+// needs the second field buffer qfield_out) is taken by the damped variants.
 inline bool multi_step_supports(const StepConfig &c) {
   if (c.channel) return false;
-  if (!c.qfield || c.variant == 0 || c.variant == 4) return true;
-  if (c.qalpha != 0.0) return false;
+  if (!c.qfield) return true;
+  const bool damped = c.variant >= 1 && c.variant <= 3;
+  if (c.qalpha == 0.0 && !damped) return true;
+  if (!damped) return false;
   if (c.storage == 0)
     return c.s[0] == 0.0 && c.s[1] == 0.0 && c.s[2] == 0.0 && c.n == c.m;
   return (float)c.s[0] == 0.0f && (float)c.s[1] == 0.0f && (float)c.s[2] == 0.0f &&

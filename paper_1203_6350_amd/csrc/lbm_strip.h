@@ -55,9 +55,14 @@ constexpr int CHI_RUNTIME = 4;
 // V_QF: a per-cell reference state (fixed in time) replaces the uniform
 // q_ref: three planes of the reference's conserved-moment deviations, read
 // per row like a sponge field (only with V_DEF and the damped variants).
+// V_QA (with V_QF): the reference follows the cells' pre-collision
+// conserved moments as a running mean, c^f <- c^f + alpha (c - c^f), after
+// each step's collision; a launch reads the field and writes the updated
+// one to a second buffer (strips read their neighbours' entries as halo).
 constexpr int V_MASK = 7;
 constexpr int V_DEF = 8;
 constexpr int V_QF = 16;
+constexpr int V_QA = 32;
 
 template <int K>
 constexpr int strip_width() {
@@ -152,9 +157,12 @@ struct StripCtx {
   CollideParams<C> p;
   C mref[9];
   const C *qf;         // V_QF: [3][qps] reference-state deviations, rows of `pitch`
+  C *qf_out;           // V_QA: the field after the launch's K steps
   int64_t qps;
+  C alpha;             // V_QA: running-mean rate
 
   static constexpr bool QF = (VAR & V_QF) != 0;
+  static constexpr bool QA = (VAR & V_QA) != 0;
 
   __device__ __forceinline__ int wrap_row(int r) const {
     r %= ny;
@@ -221,18 +229,32 @@ struct StripCtx {
       st.qraw[md<6>(Q)][2] = qf[2 * qps + cell];
     }
   }
-  // The collision of a cell of the row in ring slot Q.
+  // The collision of a cell of the row in ring slot Q; with a running-mean
+  // reference the slot then holds the cell's updated reference.
   template <int Q>
-  __device__ __forceinline__ void collide_at(const StripState<C, K> &st, C g[9]) const {
+  __device__ __forceinline__ void collide_at(StripState<C, K> &st, C g[9]) const {
     const C chi = chi_of(st.craw[md<6>(Q)]);
     if constexpr (QF) {
       CollideParams<C> pc = p;
       pc.dcf0 = st.qraw[md<6>(Q)][0];
       pc.dcf1 = st.qraw[md<6>(Q)][1];
       pc.dcf2 = st.qraw[md<6>(Q)][2];
+      // pre-collision conserved moments (rows 0-2 of M, summed as the
+      // collision sums them)
+      C dr = C(0), djx = C(0), djy = C(0);
+      if constexpr (QA) {
+        dr = g[0] + ((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
+        djx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
+        djy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+      }
       C mr[9];
       if ((VAR & V_MASK) == V_I || (VAR & V_MASK) == V_II) ref_moments(pc, mr);
       collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(g, chi, pc, mr);
+      if constexpr (QA) {
+        st.qraw[md<6>(Q)][0] = fmaC(alpha, dr - pc.dcf0, pc.dcf0);
+        st.qraw[md<6>(Q)][1] = fmaC(alpha, djx - pc.dcf1, pc.dcf1);
+        st.qraw[md<6>(Q)][2] = fmaC(alpha, djy - pc.dcf2, pc.dcf2);
+      }
     } else {
       collide<C, VAR & V_MASK, (VAR & V_DEF) != 0>(g, chi, p, mref);
     }
@@ -316,6 +338,12 @@ struct StripCtx {
         if (store_lane) {
 #pragma unroll
           for (int i = 0; i < 9; ++i) st_out(i, a - K, o[i]);
+          if constexpr (QA) {
+            const int64_t cell = (int64_t)(a - K) * pitch + X0 + (threadIdx.x & 63) - K;
+            qf_out[cell] = st.qraw[md<6>(P - K)][0];
+            qf_out[qps + cell] = st.qraw[md<6>(P - K)][1];
+            qf_out[2 * qps + cell] = st.qraw[md<6>(P - K)][2];
+          }
         }
       } else {
         chain<P, J, j + 1>(st, o, a);
@@ -337,11 +365,15 @@ __device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S
                                             const typename Store<S>::C inv_scale[9],
                                             const CollideParams<typename Store<S>::C> &p,
                                             const typename Store<S>::C *qf = nullptr,
-                                            int64_t qps = 0) {
+                                            int64_t qps = 0,
+                                            typename Store<S>::C *qf_out = nullptr,
+                                            typename Store<S>::C alpha = 0) {
   typedef typename Store<S>::C C;
   constexpr int W = strip_width<K>();
   c.qf = qf;
   c.qps = qps;
+  c.qf_out = qf_out;
+  c.alpha = alpha;
   const int lane = threadIdx.x & 63;
   c.src = src;
   c.dst = dst;
@@ -443,7 +475,8 @@ __global__ __launch_bounds__(512) void step_multi_strip(
     const typename Store<S>::C *__restrict__ chi_field,
     const typename Store<S>::C *__restrict__ chix,
     const typename Store<S>::C *__restrict__ chiy, const typename Store<S>::C *__restrict__ qf,
-    int64_t qps, int rows_per_chunk, int nstrips, int ngroups, int wg_per_xcd, int nwg) {
+    typename Store<S>::C *__restrict__ qf_out, int64_t qps, typename Store<S>::C alpha,
+    int rows_per_chunk, int nstrips, int ngroups, int wg_per_xcd, int nwg) {
   // XCD-aware order: workgroup i runs on XCD i % 8; give each XCD a
   // contiguous range of work (a band of chunk rows) so neighbouring strips
   // and chunks share an L2
@@ -457,7 +490,7 @@ __global__ __launch_bounds__(512) void step_multi_strip(
   const int Y0 = chunk * rows_per_chunk;
   StripCtx<S, VAR, CHI, K> c;
   strip_setup(c, src, dst, L.nx, L.ny, L.pitch, L.ps, strip, idle, Y0, nw, chi_field, chix, chiy,
-              CHI, L.scale, L.inv_scale, p, qf, qps);
+              CHI, L.scale, L.inv_scale, p, qf, qps, qf_out, alpha);
   strip_run(c, min(rows_per_chunk, L.ny - Y0));
 }
 
@@ -566,8 +599,8 @@ static hipError_t launch_multi_t(const StepConfig &c, const void *src, void *dst
   if (8 * per_xcd > 0x7fffffff) return hipErrorInvalidValue;
   step_multi_strip<S, VAR, CHI, K><<<dim3((unsigned)(8 * per_xcd)), dim3(64 * nw), 0, stream>>>(
       (const S *)src, (S *)dst, L, p, (const C *)c.chi_field, (const C *)c.chi_x,
-      (const C *)c.chi_y, (const C *)c.qfield, c.qps, rows, nstrips, ngroups, (int)per_xcd,
-      (int)nwg);
+      (const C *)c.chi_y, (const C *)c.qfield, (C *)c.qfield_out, c.qps, C(c.qalpha), rows,
+      nstrips, ngroups, (int)per_xcd, (int)nwg);
   return hipGetLastError();
 }
 
@@ -638,6 +671,14 @@ hipError_t launch_multi_storage(const StepConfig &c, int k, const void *src, voi
   if (c.qfield && (c.variant == V_I || c.variant == V_II || c.variant == V_III)) {
     // a per-cell reference state: the default form only (multi_step_supports)
     if (!def) return hipErrorInvalidValue;
+    if (c.qalpha != 0.0) {
+      if (!c.qfield_out) return hipErrorInvalidValue;
+      switch (c.variant) {
+        case V_I: { LBM_CHI(V_I | V_DEF | V_QF | V_QA) }
+        case V_II: { LBM_CHI(V_II | V_DEF | V_QF | V_QA) }
+        case V_III: { LBM_CHI(V_III | V_DEF | V_QF | V_QA) }
+      }
+    }
     switch (c.variant) {
       case V_I: { LBM_CHI(V_I | V_DEF | V_QF) }
       case V_II: { LBM_CHI(V_II | V_DEF | V_QF) }

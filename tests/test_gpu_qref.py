@@ -236,3 +236,65 @@ def test_reference_field_other_parameters_use_one_step_kernel():
                                  chi=chi, variant="II", s=kw.get("s", oracle.S_MRT_DEFAULT),
                                  n=kw.get("shift_n", 0.5), m=kw.get("shift_m", 0.5))
         assert rel_max(got, ref) <= 1e-12, kw
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("variant", ["II", "I", "III", "none", "visc"])
+def test_running_mean_reference_in_strip_kernels_bitwise(storage, variant):
+    """The running-mean reference in the strip kernels (each launch reads the
+    field and writes the updated one to a second buffer): populations and
+    field bit-identical to the one-cell kernel's in-place update for every
+    strip shape and sponge form, over whole launches and a remainder, and
+    across a later change of alpha; FP64 against the oracle."""
+    nx, ny = 101, 31
+    say("case: running-mean reference in strips", storage, variant)
+    rho, ux, uy, chi, q = case(nx, ny, 70 + len(variant))
+    if variant == "I":
+        chi = np.minimum(chi, 0.1)
+    if variant == "visc":
+        chi = np.minimum(chi, 1.0)
+    g = np.random.default_rng(19)
+    cx = np.minimum(g.uniform(0, 0.3, nx) * (g.uniform(size=nx) < 0.4), chi.max() / 2)
+    cy = np.minimum(g.uniform(0, 0.3, ny) * (g.uniform(size=ny) < 0.4), chi.max() / 2)
+    for form in ("field", "sum"):
+        results = []
+        for t in [dict(kernel=0, block=256)] + STRIP_TUNINGS:
+            lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage=storage, variant=variant,
+                              ux_base=0.04, f16_scale=1e-3)
+            if form == "field":
+                lat.set_sponge(chi, (1.0, 0.04, 0.0))
+            else:
+                lat.set_sponge_separable(cx, cy, form, (1.0, 0.04, 0.0))
+            lat.set_qref_field(*q)
+            lat.set_tuning(**t)
+            lat.set_qref_average(0.03)
+            lat.step(9)
+            lat.set_qref_average(0.5)
+            lat.step(6)
+            results.append((lat.save_state(), np.stack(lat.qref_field())))
+            if storage == "f64" and form == "field" and t == STRIP_TUNINGS[-1]:
+                got = lat.populations()
+            lat.close()
+        for t, (st, qf) in zip(STRIP_TUNINGS, results[1:]):
+            assert (st == results[0][0]).all(), (form, t)
+            assert np.array_equal(qf, results[0][1]), (form, t)
+    if storage == "f64":
+        f0 = oracle.feq_field(rho, ux, uy)
+        ref, cf = oracle.step_avg(f0, conserved(q), 9, alpha=0.03, chi=chi, variant=variant)
+        ref, cf = oracle.step_avg(ref, cf, 6, alpha=0.5, chi=chi, variant=variant)
+        assert rel_max(got, ref) <= 1e-12
+
+
+def test_autotune_keeps_running_mean_reference():
+    nx, ny = 130, 40
+    rho, ux, uy, chi, q = case(nx, ny, 91)
+    lat = lbm.Lattice(nx, ny, rho=rho, ux=ux, uy=uy, storage="f32", variant="II", ux_base=0.04)
+    lat.set_sponge(chi, (1.0, 0.04, 0.0))
+    lat.set_qref_field(*q)
+    lat.set_qref_average(0.1)
+    lat.step(5)
+    before = (lat.save_state(), np.stack(lat.qref_field()))
+    lat.autotune(reps=2)
+    assert (lat.save_state() == before[0]).all()
+    assert np.array_equal(np.stack(lat.qref_field()), before[1])
+    lat.close()
