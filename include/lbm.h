@@ -198,10 +198,14 @@ int lbm_get_info(lbm_handle *h, lbm_info *info);
  * (rho_f > 0, all finite), copied to the device as the conserved moments
  * (rho^f, rho^f u^f) in the compute precision; it replaces the uniform q_ref
  * of lbm_set_sponge until cleared with three NULL arrays (which also sets
- * the averaging rate back to 0). While a field is set, lbm_step runs the
- * one-cell-per-thread kernel whatever the tuning, the handle cannot join a
- * batch, and the field is not part of lbm_save_state (read it with
- * lbm_get_qref_field).
+ * the averaging rate back to 0). While a field is set, the K-step kernels
+ * of the tuning run only with the default-form parameters (conserved rates
+ * s0 = s1 = s2 = 0 and shift_n = shift_m; for a running mean also a damped
+ * variant I, II or III), lbm_step takes the one-cell-per-thread kernel
+ * otherwise (same results either way); the handle cannot join a batch, and
+ * the field is not part of lbm_save_state (read it with
+ * lbm_get_qref_field). A running mean in the K-step kernels keeps a second
+ * field buffer (allocated at the first such step).
  *
  * lbm_set_qref_average: after each step's collision the field follows the
  * cell's pre-collision conserved moments c = (rho, j) as an exponential
