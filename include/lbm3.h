@@ -83,6 +83,13 @@ int lbm3_moments(lbm3_handle *h, double *rho, double *ux, double *uy, double *uz
 int lbm3_set_tuning(lbm3_handle *h, int32_t kernel, int32_t block);
 int lbm3_get_tuning(lbm3_handle *h, int32_t *kernel, int32_t *block);
 
+/* Time every available launch shape on the handle's own lattice (reps >= 1
+ * steps each, after one untimed step; the state is left as it was: each
+ * candidate reads the current lattice and writes the other one), keep the
+ * fastest and report it (any output may be NULL). Synchronises. */
+int lbm3_autotune(lbm3_handle *h, int32_t reps, int32_t *kernel, int32_t *block,
+                  double *ms_per_step);
+
 /* Number of steps taken since creation or the last lbm3_set_populations. */
 int lbm3_steps_done(lbm3_handle *h, int64_t *steps);
 

@@ -1622,6 +1622,54 @@ int lbm3_set_tuning(lbm3_handle *h, int32_t kernel, int32_t block) {
   return LBM_OK;
 }
 
+int lbm3_autotune(lbm3_handle *h, int32_t reps, int32_t *kernel, int32_t *block,
+                  double *ms_per_step) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  const int saved_k = h->cfg.kernel, saved_b = h->cfg.block;
+  double best_t = 1e300;
+  int best_k = saved_k, best_b = saved_b;
+  for (int k = 0; k <= 1 && e == hipSuccess; ++k) {
+    if (k == 1 && h->user.nx % 2) break;
+    for (int b = 64; b <= 512 && e == hipSuccess; b *= 2) {
+      h->cfg.kernel = k;
+      h->cfg.block = b;
+      for (int r = 0; r < 1 + reps && e == hipSuccess; ++r) {
+        if (r == 1) e = hipEventRecord(e0, h->stream);
+        if (e == hipSuccess)
+          e = lbm::launch_step3(h->cfg, h->lat[h->cur], h->lat[1 - h->cur], h->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms / reps < best_t) {
+        best_t = ms / reps;
+        best_k = k;
+        best_b = b;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->cfg.kernel = saved_k;
+  h->cfg.block = saved_b;
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  h->cfg.kernel = best_k;
+  h->cfg.block = best_b;
+  if (kernel) *kernel = best_k;
+  if (block) *block = best_b;
+  if (ms_per_step) *ms_per_step = best_t;
+  return LBM_OK;
+}
+
 int lbm3_get_tuning(lbm3_handle *h, int32_t *kernel, int32_t *block) {
   if (!h || !kernel || !block) return fail(LBM_EINVAL, "NULL argument");
   *kernel = h->cfg.kernel;

@@ -155,6 +155,7 @@ def load(path: str | None = None):
         "lbm3_steps_done": [_H, ctypes.POINTER(i64)],
         "lbm3_set_tuning": [_H, i32, i32],
         "lbm3_get_tuning": [_H, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "lbm3_autotune": [_H, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), _DP],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -721,6 +722,12 @@ def lbm3_get_tuning(h):
     return {"kernel": k.value, "block": b.value}
 
 
+def lbm3_autotune(h, reps=5):
+    k, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load().lbm3_autotune(h, int(reps), ctypes.byref(k), ctypes.byref(b), ctypes.byref(ms)))
+    return {"kernel": k.value, "block": b.value}, ms.value
+
+
 def lbm3_destroy(h):
     load().lbm3_destroy(h)
 
@@ -763,6 +770,9 @@ class Lattice3:
 
     def tuning(self):
         return lbm3_get_tuning(self.h)
+
+    def autotune(self, reps=5):
+        return lbm3_autotune(self.h, reps)
 
     def close(self):
         if self.h is not None:

@@ -339,3 +339,17 @@ def test_bad_launch_shape_rejected():
     assert lat.tuning() == {"kernel": 0, "block": 256}
     lat.set_tuning(kernel=1, block=128)
     lat.close()
+
+
+def test_autotune_keeps_state():
+    nx, ny, nz = 48, 20, 12
+    F = noisy_fields(nx, ny, nz, 95)
+    lat = lbm.Lattice3(nx, ny, nz, rho=F[0], ux=F[1], uy=F[2], uz=F[3], storage="f32", **UB)
+    lat.set_sponge(wl.sponge_3d(*profiles(nx, ny, nz, 0.3)), QREF)
+    lat.step(3)
+    before = lat.populations()
+    best, ms = lat.autotune(reps=2)
+    assert ms > 0 and best == lat.tuning() and best["kernel"] in (0, 1)
+    assert np.array_equal(lat.populations(), before)
+    assert lat.steps_done() == 3
+    lat.close()
