@@ -14,8 +14,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip", "lbm_batch.hip",
-           "lbm_strip_f64.hip", "lbm_strip_f32.hip", "lbm_strip_f16.hip", "lbm3_kernels.hip"]
+# (source, extra flags, object name): the strip kernels compile once per
+# step count K, so that the largest translation units build side by side
+SOURCES = [(f, [], f.rsplit(".", 1)[0]) for f in
+           ("lbm_api.cpp", "lbm_kernels.hip", "lbm_vn.hip", "lbm_batch.hip", "lbm3_kernels.hip")]
+SOURCES += [("lbm_strip_%s.hip" % st, ["-DLBM_STRIP_ONLY_K=%d" % k], "lbm_strip_%s_k%d" % (st, k))
+            for st in ("f32", "f64", "f16") for k in (4, 3, 2)]
 
 # - no automatic FMA contraction: the kernels place their fused multiply-adds
 #   explicitly, so every launch shape gives the same bits;
@@ -40,9 +44,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(bdir, exist_ok=True)
     cc = hipcc()
     cmds, objs = [], []
-    for src in SOURCES:
-        obj = os.path.join(bdir, src.rsplit(".", 1)[0] + ".o")
-        cmds.append([cc, "-x", "hip"] + [f for f in FLAGS if f != "-shared"] + [
+    for src, extra, name in SOURCES:
+        obj = os.path.join(bdir, name + ".o")
+        cmds.append([cc, "-x", "hip"] + [f for f in FLAGS if f != "-shared"] + extra + [
             "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     # the translation units are independent: compile them side by side

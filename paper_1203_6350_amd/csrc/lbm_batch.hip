@@ -119,20 +119,36 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
 hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
                               const int4 *items, const int *nitems, int grid, int j,
                               hipStream_t stream) {
+#define LBM_BMULTI_K(ST)                                                                      \
+  switch (k) {                                                                                \
+    case 2: return launch_batch_multi_##ST##_k2(nw, def, doms, items, nitems, grid, j, stream); \
+    case 3: return launch_batch_multi_##ST##_k3(nw, def, doms, items, nitems, grid, j, stream); \
+    case 4: return launch_batch_multi_##ST##_k4(nw, def, doms, items, nitems, grid, j, stream); \
+  }                                                                                           \
+  return hipErrorInvalidValue;
   switch (storage) {
-    case 0: return launch_batch_multi_f64(k, nw, def, doms, items, nitems, grid, j, stream);
-    case 1: return launch_batch_multi_f32(k, nw, def, doms, items, nitems, grid, j, stream);
-    case 2: return launch_batch_multi_f16(k, nw, def, doms, items, nitems, grid, j, stream);
+    case 0: { LBM_BMULTI_K(f64) }
+    case 1: { LBM_BMULTI_K(f32) }
+    case 2: { LBM_BMULTI_K(f16) }
   }
+#undef LBM_BMULTI_K
   return hipErrorInvalidValue;
 }
 
 int batch_multi_per_cu(int storage, int k, int nw, bool def) {
+#define LBM_BPERCU_K(ST)                                        \
+  switch (k) {                                                  \
+    case 2: return batch_multi_per_cu_##ST##_k2(nw, def);       \
+    case 3: return batch_multi_per_cu_##ST##_k3(nw, def);       \
+    case 4: return batch_multi_per_cu_##ST##_k4(nw, def);       \
+  }                                                             \
+  return 0;
   switch (storage) {
-    case 0: return batch_multi_per_cu_f64(k, nw, def);
-    case 1: return batch_multi_per_cu_f32(k, nw, def);
-    case 2: return batch_multi_per_cu_f16(k, nw, def);
+    case 0: { LBM_BPERCU_K(f64) }
+    case 1: { LBM_BPERCU_K(f32) }
+    case 2: { LBM_BPERCU_K(f16) }
   }
+#undef LBM_BPERCU_K
   return 0;
 }
 

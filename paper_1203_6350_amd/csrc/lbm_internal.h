@@ -63,12 +63,17 @@ inline bool multi_step_supports(const StepConfig &c) {
 hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void *dst,
                               hipStream_t stream);
 // per storage type (lbm_strip_f64/f32/f16.hip)
-hipError_t launch_multi_f64(const StepConfig &c, int k, const void *src, void *dst,
-                            hipStream_t stream);
-hipError_t launch_multi_f32(const StepConfig &c, int k, const void *src, void *dst,
-                            hipStream_t stream);
-hipError_t launch_multi_f16(const StepConfig &c, int k, const void *src, void *dst,
-                            hipStream_t stream);
+// Per storage type and step count (lbm_strip_f64/f32/f16.hip, one object
+// per K): the single-lattice strip launch, the batched one and its
+// resident workgroups per CU.
+#define LBM_STRIP_DECL(ST, K)                                                                    \
+  hipError_t launch_multi_##ST##_k##K(const StepConfig &c, const void *src, void *dst,          \
+                                      hipStream_t stream);                                       \
+  hipError_t launch_batch_multi_##ST##_k##K(int nw, bool def, const BatchDomain *doms,          \
+                                            const int4 *items, const int *nitems, int grid,     \
+                                            int j, hipStream_t stream);                          \
+  int batch_multi_per_cu_##ST##_k##K(int nw, bool def);
+#define LBM_STRIP_DECL_K(ST) LBM_STRIP_DECL(ST, 2) LBM_STRIP_DECL(ST, 3) LBM_STRIP_DECL(ST, 4)
 bool vec_supported(const StepConfig &c);
 // FP16 mode: stored value = deviation / storage_scale (a power of two).
 double storage_scale(const StepConfig &c, int i);
@@ -125,18 +130,9 @@ hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchD
                               const int4 *items, const int *nitems, int grid, int j,
                               hipStream_t stream);
 int batch_multi_per_cu(int storage, int k, int nw, bool def);
-hipError_t launch_batch_multi_f64(int k, int nw, bool def, const BatchDomain *doms,
-                                  const int4 *items, const int *nitems, int grid, int j,
-                                  hipStream_t stream);
-hipError_t launch_batch_multi_f32(int k, int nw, bool def, const BatchDomain *doms,
-                                  const int4 *items, const int *nitems, int grid, int j,
-                                  hipStream_t stream);
-hipError_t launch_batch_multi_f16(int k, int nw, bool def, const BatchDomain *doms,
-                                  const int4 *items, const int *nitems, int grid, int j,
-                                  hipStream_t stream);
-int batch_multi_per_cu_f64(int k, int nw, bool def);
-int batch_multi_per_cu_f32(int k, int nw, bool def);
-int batch_multi_per_cu_f16(int k, int nw, bool def);
+LBM_STRIP_DECL_K(f64)
+LBM_STRIP_DECL_K(f32)
+LBM_STRIP_DECL_K(f16)
 
 // Three-dimensional D3Q15 step (lbm3_kernels.hip): everything a kernel
 // needs in FP64, converted per launch to the compute precision.

@@ -408,12 +408,19 @@ hipError_t launch_step(const StepConfig &c, const void *src, void *dst,
 
 hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void *dst,
                               hipStream_t stream) {
-  if (k < 2 || k > 4) return hipErrorInvalidValue;
+#define LBM_MULTI_K(ST)                                                \
+  switch (k) {                                                         \
+    case 2: return launch_multi_##ST##_k2(c, src, dst, stream);        \
+    case 3: return launch_multi_##ST##_k3(c, src, dst, stream);        \
+    case 4: return launch_multi_##ST##_k4(c, src, dst, stream);        \
+  }                                                                    \
+  return hipErrorInvalidValue;
   switch (c.storage) {
-    case 0: return launch_multi_f64(c, k, src, dst, stream);
-    case 1: return launch_multi_f32(c, k, src, dst, stream);
-    case 2: return launch_multi_f16(c, k, src, dst, stream);
+    case 0: { LBM_MULTI_K(f64) }
+    case 1: { LBM_MULTI_K(f32) }
+    case 2: { LBM_MULTI_K(f16) }
   }
+#undef LBM_MULTI_K
   return hipErrorInvalidValue;
 }
 

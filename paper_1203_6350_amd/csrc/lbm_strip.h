@@ -604,13 +604,41 @@ static hipError_t launch_multi_t(const StepConfig &c, const void *src, void *dst
   return hipGetLastError();
 }
 
+// A translation unit may instantiate the kernels of one step count only
+// (LBM_STRIP_ONLY_K), so that the step counts compile side by side.
+template <int K>
+static constexpr bool strip_k_built() {
+#ifdef LBM_STRIP_ONLY_K
+  return K == LBM_STRIP_ONLY_K;
+#else
+  return true;
+#endif
+}
+
+template <typename S, int VAR, int CHI, int K>
+static hipError_t launch_multi_k(const StepConfig &c, const void *src, void *dst,
+                                 hipStream_t stream) {
+  if constexpr (strip_k_built<K>()) return launch_multi_t<S, VAR, CHI, K>(c, src, dst, stream);
+  return hipErrorInvalidValue;
+}
+
 template <typename S, int VAR, int CHI>
 static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void *dst,
                                hipStream_t stream) {
   switch (k) {
-    case 2: return launch_multi_t<S, VAR, CHI, 2>(c, src, dst, stream);
-    case 3: return launch_multi_t<S, VAR, CHI, 3>(c, src, dst, stream);
-    case 4: return launch_multi_t<S, VAR, CHI, 4>(c, src, dst, stream);
+    case 2: return launch_multi_k<S, VAR, CHI, 2>(c, src, dst, stream);
+    case 3: return launch_multi_k<S, VAR, CHI, 3>(c, src, dst, stream);
+    case 4: return launch_multi_k<S, VAR, CHI, 4>(c, src, dst, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename S, int K, bool DEF>
+static hipError_t launch_batch_multi_k(int nw, const BatchDomain *doms, const int4 *items,
+                                       const int *nitems, int grid, int j, hipStream_t s) {
+  if constexpr (strip_k_built<K>()) {
+    batch_multi_strip<S, K, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j);
+    return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
@@ -619,43 +647,52 @@ template <typename S, bool DEF>
 static hipError_t launch_batch_multi_t(int k, int nw, const BatchDomain *doms, const int4 *items,
                                        const int *nitems, int grid, int j, hipStream_t s) {
   switch (k) {
-    case 2: batch_multi_strip<S, 2, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
-    case 3: batch_multi_strip<S, 3, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
-    case 4: batch_multi_strip<S, 4, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j); break;
-    default: return hipErrorInvalidValue;
+    case 2: return launch_batch_multi_k<S, 2, DEF>(nw, doms, items, nitems, grid, j, s);
+    case 3: return launch_batch_multi_k<S, 3, DEF>(nw, doms, items, nitems, grid, j, s);
+    case 4: return launch_batch_multi_k<S, 4, DEF>(nw, doms, items, nitems, grid, j, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
+// (Internal linkage: each translation unit builds its own step counts.)
 template <typename S>
-hipError_t launch_batch_multi_storage(int k, int nw, bool def, const BatchDomain *doms,
+static hipError_t launch_batch_multi_storage(int k, int nw, bool def, const BatchDomain *doms,
                                       const int4 *items, const int *nitems, int grid, int j,
                                       hipStream_t s) {
   return def ? launch_batch_multi_t<S, true>(k, nw, doms, items, nitems, grid, j, s)
              : launch_batch_multi_t<S, false>(k, nw, doms, items, nitems, grid, j, s);
 }
 
+template <typename S, int K, bool DEF>
+static int batch_multi_per_cu_k(int nw) {
+  int per_cu = 0;
+  if constexpr (strip_k_built<K>()) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, K, DEF>,
+                                                     64 * nw, 0) != hipSuccess)
+      return 0;
+  }
+  return per_cu;
+}
+
 template <typename S, bool DEF>
 static int batch_multi_per_cu_t(int k, int nw) {
-  int per_cu = 0;
-  hipError_t e = hipErrorInvalidValue;
   switch (k) {
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 2, DEF>, 64 * nw, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 3, DEF>, 64 * nw, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, 4, DEF>, 64 * nw, 0); break;
+    case 2: return batch_multi_per_cu_k<S, 2, DEF>(nw);
+    case 3: return batch_multi_per_cu_k<S, 3, DEF>(nw);
+    case 4: return batch_multi_per_cu_k<S, 4, DEF>(nw);
   }
-  return e == hipSuccess ? per_cu : 0;
+  return 0;
 }
 
 // Workgroups of nw waves of the batched multi-step kernel resident per CU.
 template <typename S>
-int batch_multi_per_cu(int k, int nw, bool def) {
+static int batch_multi_per_cu(int k, int nw, bool def) {
   return def ? batch_multi_per_cu_t<S, true>(k, nw) : batch_multi_per_cu_t<S, false>(k, nw);
 }
 
 // All variants, sponge forms and step counts of one storage type.
 template <typename S>
-hipError_t launch_multi_storage(const StepConfig &c, int k, const void *src, void *dst,
+static hipError_t launch_multi_storage(const StepConfig &c, int k, const void *src, void *dst,
                                 hipStream_t s) {
 #define LBM_CHI(VAR)                                                          \
   switch (c.chi_mode) {                                                       \

@@ -1,19 +1,34 @@
-// lbm_strip_f32.hip -- multi-step strip kernels for FP32 storage.
+// lbm_strip_f32.hip -- multi-step strip kernels for F32 storage. The
+// build compiles this file once per step count K (LBM_STRIP_ONLY_K = 2, 3,
+// 4), each object exporting the K-suffixed entry points that
+// launch_multi_steps and the batch dispatch call.
 #include "lbm_strip.h"
+
+#ifndef LBM_STRIP_ONLY_K
+#error "compile with -DLBM_STRIP_ONLY_K=2, 3 or 4"
+#endif
+
+#define LBM_CAT2(a, b) a##b
+#define LBM_CAT(a, b) LBM_CAT2(a, b)
 
 namespace lbm {
 
-hipError_t launch_multi_f32(const StepConfig &c, int k, const void *src, void *dst,
-                          hipStream_t stream) {
-  return launch_multi_storage<float>(c, k, src, dst, stream);
+hipError_t LBM_CAT(launch_multi_f32_k, LBM_STRIP_ONLY_K)(const StepConfig &c, const void *src,
+                                                          void *dst, hipStream_t stream) {
+  return launch_multi_storage<float>(c, LBM_STRIP_ONLY_K, src, dst, stream);
 }
 
-hipError_t launch_batch_multi_f32(int k, int nw, bool def, const BatchDomain *doms,
-                                const int4 *items, const int *nitems, int grid, int j,
-                                hipStream_t stream) {
-  return launch_batch_multi_storage<float>(k, nw, def, doms, items, nitems, grid, j, stream);
+hipError_t LBM_CAT(launch_batch_multi_f32_k, LBM_STRIP_ONLY_K)(int nw, bool def,
+                                                                const BatchDomain *doms,
+                                                                const int4 *items,
+                                                                const int *nitems, int grid,
+                                                                int j, hipStream_t stream) {
+  return launch_batch_multi_storage<float>(LBM_STRIP_ONLY_K, nw, def, doms, items, nitems, grid,
+                                           j, stream);
 }
 
-int batch_multi_per_cu_f32(int k, int nw, bool def) { return batch_multi_per_cu<float>(k, nw, def); }
+int LBM_CAT(batch_multi_per_cu_f32_k, LBM_STRIP_ONLY_K)(int nw, bool def) {
+  return batch_multi_per_cu<float>(LBM_STRIP_ONLY_K, nw, def);
+}
 
 }  // namespace lbm
