@@ -61,6 +61,30 @@ def kernel_hash(family):
     return h.hexdigest()[:16]
 
 
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "step_f32_typeII_4096_valu.txt")
+
+
+def valu_issue(tuning):
+    """VALU issue-busy fraction and lane-instructions per cell update of the
+    four-step kernel from the committed SQ-counter summary, or None when the
+    strip sources changed since or another launch shape runs."""
+    if not os.path.exists(VALU_SUMMARY) or tuning.get("kernel") != 4:
+        return None
+    txt = open(VALU_SUMMARY).read()
+    m = re.search(r"strip_kernel_sources_sha256_16:\s*(\w+)", txt)
+    t = re.search(r"--tuning (\d+),(\d+),(\d+)", txt)
+    busy = re.search(r"= ([0-9.]+)\s*$", txt.split("VALU issue busy:")[1].splitlines()[0]) \
+        if "VALU issue busy:" in txt else None
+    lane = re.search(r"-> ([0-9.]+) lane-instructions per cell update", txt)
+    if not (m and t and busy and lane) or m.group(1) != kernel_hash("strip"):
+        return None
+    if (int(t.group(1)), int(t.group(2)), int(t.group(3))) != (
+            tuning["kernel"], tuning["block"], tuning.get("rows", 0)):
+        return None
+    return {"valu_issue_busy": float(busy.group(1)),
+            "lane_instructions_per_update": float(lane.group(1))}
+
+
 def counter_traffic(tuning):
     """HBM bytes per launch of the given launch shape from the committed
     rocprofv3 --pmc summary, or None when the kernel source changed since the
@@ -622,9 +646,14 @@ def main():
               "alu_tflops": alu_tflops, "alu_frac": alu_tflops / PEAK_VALU_TFLOPS,
               "single_step_equivalent_gbps": bytes_per_cell * r["mlups"] / 1e3}
     if per >= 3:
-        # three or more steps per launch: the vector ALUs, not HBM, bound it
+        # three or more steps per launch: the vector ALUs, not HBM, bound it;
+        # the SQ counters give the issue utilisation the flop rate understates
         roofline = dict({"bound": "alu", "achieved": alu_tflops, "peak": PEAK_VALU_TFLOPS,
                          "unit": "TFLOP/s", "frac": alu_tflops / PEAK_VALU_TFLOPS}, **common)
+        issue = (valu_issue(r["tuning"]) if args.storage == "f32" and args.n == 4096
+                 and head == "II" else None)
+        if issue:
+            roofline.update(issue)
     else:
         roofline = dict({"bound": "hbm", "achieved": hbm_gbps, "peak": PEAK_HBM_GBPS,
                          "unit": "GB/s", "frac": hbm_gbps / PEAK_HBM_GBPS}, **common)
