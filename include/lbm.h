@@ -248,7 +248,8 @@ typedef struct lbm_tuning {
                           once per launch; a shorter remainder of steps
                           runs as one launch of that many steps, a single
                           remaining step with kernel 0)                      */
-  int32_t block;       /* threads per block: 64, 128, 256 or 512            */
+  int32_t block;       /* threads per block: 64, 128, 256 or 512 (FP64
+                          storage with kernel 4: at most 256)               */
   int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
   int32_t rows;        /* kernels 2-4: rows per chunk, 1..4096, or 0 for
                           the height at which all blocks are resident at

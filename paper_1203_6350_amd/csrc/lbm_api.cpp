@@ -590,6 +590,8 @@ int lbm_set_tuning(lbm_handle *h, const lbm_tuning *t) {
   if (t->nontemporal != 0 && t->nontemporal != 1) return fail(LBM_EINVAL, "nontemporal must be 0 or 1");
   if (t->kernel >= 2 && (t->rows < 0 || t->rows > 4096))
     return fail(LBM_EINVAL, "rows must be 0 (fit the device) or 1..4096");
+  if (t->kernel >= 2 && t->block > lbm::multi_step_max_block(h->user.storage, t->kernel))
+    return fail(LBM_EINVAL, "FP64 storage with four steps per launch takes blocks of at most 256");
   h->cfg.kernel = t->kernel;
   h->cfg.block = t->block;
   h->cfg.nontemporal = t->kernel == 1 ? t->nontemporal : 0;
@@ -622,7 +624,8 @@ int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms)
   if (lbm::multi_step_supports(h->cfg))  // lbm_step would not run them otherwise
     for (int kk = lbm::KERNEL_MULTI_MIN; kk <= lbm::KERNEL_MULTI_MAX; ++kk)
       for (int b : blocks)
-        for (int r : rows) cands.push_back(lbm_tuning{kk, b, 0, r});
+        if (b <= lbm::multi_step_max_block(h->user.storage, kk))
+          for (int r : rows) cands.push_back(lbm_tuning{kk, b, 0, r});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   hipError_t e = hipEventCreate(&e1);

@@ -43,6 +43,11 @@ struct StepConfig {
 
 enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MAX = 4 };
 
+// Largest workgroup of the single-lattice K-step kernel: FP64 storage with
+// four steps per launch is built for one wave per SIMD (its registers do
+// not fit two), so its workgroups take at most 256 threads.
+constexpr int multi_step_max_block(int storage, int k) { return storage == 0 && k == 4 ? 256 : 512; }
+
 // The multi-step strip kernels take this configuration: no channel, and a
 // per-cell reference state only when the collision has its default form
 // (conserved rates 0, n = m in the compute precision). A fixed reference is

@@ -469,7 +469,7 @@ __device__ __forceinline__ void strip_run(const StripCtx<S, VAR, CHI, K> &c, int
 }
 
 template <typename S, int VAR, int CHI, int K>
-__global__ __launch_bounds__(512) void step_multi_strip(
+__global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K)) void step_multi_strip(
     const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
     CollideParams<typename Store<S>::C> p,
     const typename Store<S>::C *__restrict__ chi_field,
@@ -583,6 +583,7 @@ static hipError_t launch_multi_t(const StepConfig &c, const void *src, void *dst
   typedef typename Store<S>::C C;
   Lat<S> L = make_lat<S>(c);
   CollideParams<C> p = make_params<C>(c);
+  if (c.block > multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K)) return hipErrorInvalidValue;
   const int nw = c.block == 64 ? 1 : (c.block == 128 ? 2 : (c.block == 256 ? 4 : 8));
   const int nstrips = (c.nx + strip_width<K>() - 1) / strip_width<K>();
   const int ngroups = (nstrips + nw - 1) / nw;
