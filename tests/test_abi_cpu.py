@@ -82,6 +82,25 @@ def test_create_rejects_bad_config(bad):
     assert lbm.lbm_last_error()
 
 
+@pytest.mark.parametrize("nx,ny,ok", [
+    (46340, 46340, True), (46341, 46341, False),      # nx * ny below 2^31
+    (1 << 30, 1, True), ((1 << 30) + 1, 1, False),    # one side at most 2^30
+    (1, 1 << 30, True), (2, 1 << 30, False),
+])
+def test_size_limit_is_exact(nx, ny, ok):
+    """The largest lattices the library takes (nx * ny below 2^31, each side
+    at most 2^30) are accepted (sized on the host, nothing allocated) and
+    the next ones are rejected."""
+    cfg = lbm.make_config(nx, ny, storage="f16", f16_scale=1e-3)
+    if ok:
+        plane = -(-nx * ny * 2 // 256) * 256
+        assert lbm.lbm_required_bytes(cfg) == 2 * 9 * plane
+    else:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_required_bytes(cfg)
+        assert e.value.code == lbm.LBM_EINVAL
+
+
 def test_required_bytes_is_host_only():
     cfg = lbm.make_config(100, 30, storage="f32")
     b = lbm.lbm_required_bytes(cfg)
