@@ -247,7 +247,10 @@ typedef struct lbm_tuning {
                           adjacent strips; the lattice is read and written
                           once per launch; a shorter remainder of steps
                           runs as one launch of that many steps, a single
-                          remaining step with kernel 0)                      */
+                          remaining step with kernel 0; rows of more than
+                          2^32 bytes (FP64, nx > 2^29) always run with
+                          kernel 0: the strips address columns with 32-bit
+                          byte offsets)                                      */
   int32_t block;       /* threads per block: 64, 128, 256 or 512 (FP64
                           storage with kernel 4: at most 256)               */
   int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
@@ -280,7 +283,8 @@ const char *lbm_last_error(void);
  * a table of 256-cell tiles. A batch whose work items do not fill the
  * device once (few or small members) runs its ticks as one-step tile
  * launches only, which spread it over the whole device. All members must share the storage mode and the
- * device. Each member's result is bit-identical to stepping it alone with
+ * device; members with a per-cell reference state, a line source or rows
+ * of more than 2^32 bytes are refused (LBM_EINVAL). Each member's result is bit-identical to stepping it alone with
  * lbm_step.
  * While a batch has work in flight its members must not be used on their
  * own; lbm_batch_sync makes them usable again. Member parameters (sponge,

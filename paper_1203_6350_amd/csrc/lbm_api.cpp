@@ -426,8 +426,9 @@ int lbm_step(lbm_handle *h, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   int64_t k = 0;
   const int per = h->cfg.kernel;  // time steps per launch of the multi-step kernel
-  // a channel, a running-mean reference state, or a per-cell one with
-  // parameters other than the default form run in the one-step kernel only
+  // a channel, rows of more than 2^32 bytes, a running-mean reference state,
+  // or a per-cell one with parameters other than the default form run in the
+  // one-step kernel only
   if (per >= lbm::KERNEL_MULTI_MIN && lbm::multi_step_supports(h->cfg)) {
     // a running-mean reference: each launch writes the updated field to the
     // second buffer, which then becomes the current one
@@ -980,6 +981,8 @@ int validate_members(lbm_handle *const *members, int32_t count) {
       return fail(LBM_EINVAL, "members with a per-cell reference state are not batched");
     if (members[i]->channel)
       return fail(LBM_EINVAL, "members with a line source are not batched");
+    if (!lbm::strip_row_fits(members[i]->user.nx, members[i]->user.storage))
+      return fail(LBM_EINVAL, "members with rows of more than 2^32 bytes are not batched");
   }
   return LBM_OK;
 }

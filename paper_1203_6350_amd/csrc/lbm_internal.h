@@ -48,13 +48,22 @@ enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MA
 // not fit two), so its workgroups take at most 256 threads.
 constexpr int multi_step_max_block(int storage, int k) { return storage == 0 && k == 4 ? 256 : 512; }
 
-// The multi-step strip kernels take this configuration: no channel, and a
+// The strip kernels address a lane's column within a row as a 32-bit byte
+// offset, so they take rows of at most 2^32 bytes (FP64 rows of more than
+// 2^29 cells run in the one-cell kernels).
+inline bool strip_row_fits(int64_t nx, int storage) {
+  const int64_t eb = storage == 0 ? 8 : (storage == 1 ? 4 : 2);
+  return nx * eb <= (int64_t(1) << 32);
+}
+
+// The multi-step strip kernels take this configuration: rows that fit
+// their byte offsets, no channel, and a
 // per-cell reference state only when the collision has its default form
 // (conserved rates 0, n = m in the compute precision). A fixed reference is
 // ignored by the undamped and viscosity-ramp variants; a running mean (which
 // needs the second field buffer qfield_out) is taken by the damped variants.
 inline bool multi_step_supports(const StepConfig &c) {
-  if (c.channel) return false;
+  if (c.channel || !strip_row_fits(c.nx, c.storage)) return false;
   if (!c.qfield) return true;
   const bool damped = c.variant >= 1 && c.variant <= 3;
   if (c.qalpha == 0.0 && !damped) return true;
