@@ -369,12 +369,14 @@ def test_fp64_four_step_block_limit():
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("nx,ny,steps", [(256, 40, 20), (136, 9, 21), (2, 5, 20), (8, 3, 21),
-                                         (61, 70, 20), (300, 77, 21)])
+                                         (61, 70, 20), (300, 77, 21), (1, 6, 9), (70, 1, 9),
+                                         (1, 1, 5)])
 def test_every_tuning_bitwise_identical(storage, nx, ny, steps):
     """All launch shapes run the same per-cell arithmetic: bit-identical state,
     including the vector kernel's periodic wrap lanes and ragged tails, and
     the two-steps-per-launch strips (chunk edges, partial strips, an odd
-    final step)."""
+    final step, a single row or column whose neighbours are the cells
+    themselves)."""
     say("case: tunings", storage, nx, ny, steps)
     rho, ux, uy, chi = random_case(nx, ny, 31 + nx)
     q = (1.0, 0.04, 0.0)
