@@ -301,7 +301,8 @@ def test_full_size_cube_sampled_against_oracle(storage, bar):
 # ------------------------------------------------------------------ launch shapes
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("nx,ny,nz", [(16, 5, 3), (40, 9, 7), (8, 1, 2), (600, 3, 2), (21, 4, 3), (2, 3, 2)])
+@pytest.mark.parametrize("nx,ny,nz", [(16, 5, 3), (40, 9, 7), (8, 1, 2), (600, 3, 2), (21, 4, 3), (2, 3, 2),
+                                      (1, 4, 3), (1, 1, 1)])
 def test_every_launch_shape_bitwise_identical(storage, nx, ny, nz):
     """One and two cells per thread with every workgroup size: the same bits
     (rows shorter and longer than a workgroup, ragged tails, the periodic
