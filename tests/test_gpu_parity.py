@@ -318,6 +318,28 @@ def test_vn_matches_lapack(idx):
     np.testing.assert_allclose(np.prod(lam, axis=1), detA, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("nk", [0, 1, 15, 16, 17])
+def test_vn_empty_single_and_ragged_sweeps(nk):
+    """No wavenumbers, one, and one lane short of, at and past a workgroup's
+    16: each spectrum equals LAPACK's, and a wavenumber's result does not
+    depend on the others in its sweep."""
+    p = VN_SETS[5]
+    g = np.random.default_rng(100 + nk)
+    kx, ky = g.uniform(-np.pi, np.pi, nk), g.uniform(-np.pi, np.pi, nk)
+    lam, G = lbm.vn_amplification(p, kx, ky, want_G=True)
+    assert lam.shape[0] == nk and G.shape[0] == nk
+    if nk == 0:
+        return
+    A = vn.linearized_collision(p["s"], p["chi"], p["qref"], p["n"], p["m"], p["variant"])
+    Gr = vn.amplification(A, kx, ky)
+    np.testing.assert_allclose(G, Gr, rtol=0, atol=1e-13)
+    ref = np.linalg.eigvals(Gr)
+    for i in range(nk):
+        assert match_eigs(lam[i], ref[i]) <= 1e-10, (i, kx[i], ky[i])
+    alone = lbm.vn_amplification(p, kx[-1:], ky[-1:])
+    assert np.array_equal(alone[0], lam[-1])
+
+
 def test_vn_paper_thresholds_on_gpu():
     """Section 3.3: BGK Type II is marginal at chi = 4/s and unstable at 4/s + 0.1."""
     k = np.linspace(-np.pi, np.pi, 241)
