@@ -240,14 +240,15 @@ def test_reference_field_other_parameters_use_one_step_kernel():
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("variant", ["II", "I", "III", "none", "visc"])
-def test_running_mean_reference_in_strip_kernels_bitwise(storage, variant):
+@pytest.mark.parametrize("nx,ny", [(101, 31), (1, 7), (66, 1)])
+def test_running_mean_reference_in_strip_kernels_bitwise(storage, variant, nx, ny):
     """The running-mean reference in the strip kernels (each launch reads the
     field and writes the updated one to a second buffer): populations and
     field bit-identical to the one-cell kernel's in-place update for every
     strip shape and sponge form, over whole launches and a remainder, and
-    across a later change of alpha; FP64 against the oracle."""
-    nx, ny = 101, 31
-    say("case: running-mean reference in strips", storage, variant)
+    across a later change of alpha, also on a single column and a single
+    row; FP64 against the oracle."""
+    say("case: running-mean reference in strips", storage, variant, nx, ny)
     rho, ux, uy, chi, q = case(nx, ny, 70 + len(variant))
     if variant == "I":
         chi = np.minimum(chi, 0.1)
