@@ -599,8 +599,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: every box here has one MI355X, so "
-              "--gpus %d is not run (multi-GPU sharding is a design note)." % args.gpus,
+        print("bench.py measures one GPU only: the multi-GPU form (row bands per GPU with "
+              "a halo exchange) is designed but not built, so --gpus %d is not run." % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
