@@ -13,6 +13,10 @@ Two independent implementations live here:
 * ``vn.py`` (O2): the Von Neumann analysis of Section 3.2 in numpy, with its
   own copy of the collision written for complex arithmetic.
 
+``lbm_oracle.c`` also holds the diagnostics (the density and momentum
+deviations whose L2 norm Section 4.1 tracks, the largest population
+deviation over the finite cells, the count of non-finite cells).
+
 Population layout everywhere: ``f[9][ny][nx]`` (x fastest), velocity order of
 M's columns: c0=(0,0) c1=(1,0) c2=(0,1) c3=(-1,0) c4=(0,-1) c5=(1,1)
 c6=(-1,1) c7=(-1,-1) c8=(1,-1).
@@ -82,6 +86,9 @@ def lib():
         L.oracle_tables.argtypes = [dp, dp, ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_int), dp]
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_diagnostics.argtypes = [i64, i64, dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, dp]
+        L.oracle_diagnostics.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -224,25 +231,20 @@ def moments(f):
 
 
 def diagnostics(f, rho_b=1.0, ux_b=0.0, uy_b=0.0):
-    """FP64 reference of the diagnostics reduction.
-
-    Returns (sum drho, sum djx, sum djy, sum drho^2, sum |dj|^2, max |f - f_base|,
-    non-finite cell count), deviations taken from the base state
-    f_base = f^eq(rho_b, u_b).
+    """Monitored quantities of a pre-collision state ``f[9][ny][nx]`` against
+    the base state (rho_b, u_b) (the deviations whose L2 norm Section 4.1
+    tracks): (sum drho, sum djx, sum djy, sum drho^2, sum |dj|^2,
+    max over finite cells of |f - f^eq(rho_b, u_b)|, non-finite cell count).
     """
-    _, _, cx, cy, _ = tables()
-    rho = f.sum(axis=0)
-    jx = np.tensordot(cx.astype(np.float64), f, axes=(0, 0))
-    jy = np.tensordot(cy.astype(np.float64), f, axes=(0, 0))
-    drho = rho - rho_b
-    djx = jx - rho_b * ux_b
-    djy = jy - rho_b * uy_b
-    fb = feq_field(np.array([rho_b]), np.array([ux_b]), np.array([uy_b]))[:, 0]
-    dev = f - fb[:, None, None]
-    bad = ~np.isfinite(f).all(axis=0)
-    return np.array([drho.sum(), djx.sum(), djy.sum(), (drho ** 2).sum(),
-                     (djx ** 2 + djy ** 2).sum(), np.abs(dev).max(), bad.sum()],
-                    dtype=np.float64)
+    f = _f64(f)
+    assert f.ndim == 3 and f.shape[0] == 9
+    ny, nx = f.shape[1:]
+    out = np.empty(7)
+    rc = lib().oracle_diagnostics(nx, ny, _dp(f), float(rho_b), float(ux_b), float(uy_b),
+                                  _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_diagnostics rejected its arguments")
+    return out
 
 
 def max_threads():

@@ -431,6 +431,65 @@ int oracle_flin_field(int64_t N, const double *rho, const double *ux,
   return 0;
 }
 
+/*
+ * oracle_diagnostics -- the monitored quantities of a pre-collision state
+ * f[9][ny][nx] relative to the base state (rho_b, u_b). The density
+ * deviation delta rho = rho - rho_b is what the L2 error of Section 4.1 sums
+ * (E_L2 = sqrt(sum delta rho^2 / N) with rho_b = rho_0), and the momentum
+ * deviation delta j = j - rho_b u_b its counterpart for the flow.
+ *   out[0] = sum over cells of delta rho       (rho = sum_i f_i)
+ *   out[1] = sum of delta j_x                  (j = sum_i c_i f_i)
+ *   out[2] = sum of delta j_y
+ *   out[3] = sum of delta rho^2
+ *   out[4] = sum of |delta j|^2
+ *   out[5] = max over finite cells of max_i |f_i - f^eq_i(rho_b, rho_b u_b)|
+ *            (0 when no cell is finite)
+ *   out[6] = number of cells with a non-finite population
+ * The sums run over every cell, so a non-finite cell makes them non-finite;
+ * a cell is finite when all nine of its populations are.
+ */
+int oracle_diagnostics(int64_t nx, int64_t ny, const double *f, double rho_b,
+                       double ux_b, double uy_b, double *out) {
+  setup();
+  if (nx < 1 || ny < 1 || !f || !out) return -1;
+  const int64_t N = nx * ny;
+  double fb[Q];
+  feq(rho_b, rho_b * ux_b, rho_b * uy_b, fb);
+  double s_r = 0.0, s_jx = 0.0, s_jy = 0.0, s_r2 = 0.0, s_j2 = 0.0, mx = 0.0, bad = 0.0;
+  for (int64_t c = 0; c < N; ++c) {
+    double rho = 0.0, jx = 0.0, jy = 0.0, dmax = 0.0;
+    int finite = 1;
+    for (int i = 0; i < Q; ++i) {
+      const double v = f[i * N + c];
+      rho += v;
+      jx += CX[i] * v;
+      jy += CY[i] * v;
+      if (!isfinite(v)) finite = 0;
+      const double d = fabs(v - fb[i]);
+      if (d > dmax) dmax = d;
+    }
+    const double dr = rho - rho_b, djx = jx - rho_b * ux_b, djy = jy - rho_b * uy_b;
+    s_r += dr;
+    s_jx += djx;
+    s_jy += djy;
+    s_r2 += dr * dr;
+    s_j2 += djx * djx + djy * djy;
+    if (finite) {
+      if (dmax > mx) mx = dmax;
+    } else {
+      bad += 1.0;
+    }
+  }
+  out[0] = s_r;
+  out[1] = s_jx;
+  out[2] = s_jy;
+  out[3] = s_r2;
+  out[4] = s_j2;
+  out[5] = mx;
+  out[6] = bad;
+  return 0;
+}
+
 /* Copies of the oracle's matrices, velocities and weights for the tests. */
 int oracle_tables(double *M_out, double *Minv_out, int *cx, int *cy,
                   double *w) {

@@ -22,6 +22,12 @@ MUTANTS = {
     "type_III_unshifted": ("flin3(rs, jsx, jsy, jsz, tmp);", "flin3(rho, jx, jy, jz, tmp);"),
     "stream_z_push": ("zs = wrap3(z - C3Z[i], nz);", "zs = wrap3(z + C3Z[i], nz);"),
     "relax_sign": ("mom[k] + sk[k] * (meq[k] - mom[k]) + d[k]", "mom[k] + sk[k] * (mom[k] - meq[k]) + d[k]"),
+    "visc_ramp_wrong_end": ("sk[k] = s[k] + (1.0 - s[k]) * xi;", "sk[k] = s[k] + (2.0 - s[k]) * xi;"),
+    "visc_ramp_squared": ("sk[k] = s[k] + (1.0 - s[k]) * xi;", "sk[k] = s[k] + (1.0 - s[k]) * xi * xi;"),
+    "visc_keeps_shift": ("if (variant == V3_NONE || variant == V3_VISC) chi = 0.0;",
+                         "if (variant == V3_NONE) chi = 0.0;"),
+    "visc_ramp_read_after_zeroing": ("  const double xi = chi;\n  if (variant == V3_NONE || variant == V3_VISC) chi = 0.0;",
+                                     "  if (variant == V3_NONE || variant == V3_VISC) chi = 0.0;\n  const double xi = chi;"),
 }
 
 

@@ -182,3 +182,73 @@ def test_shear_wave_decays_at_the_mrt_viscosity(s):
     amp1 = (u1[0, :, 0] * np.sin(k * y)).sum()
     nu = CS2 * (1 / s - 0.5)
     assert abs(math.log(amp1 / amp0) / (-nu * k * k * T) - 1) < 1e-2
+
+
+# ------------------------------------------------------------------ viscosity-ramp strategy (Sec. 4.1 on App. A.2)
+
+S_RAMP = (0.0,) * 4 + (1.1, 1.25, 1.4, 1.5, 1.6, 1.7, 1.75, 1.8, 1.85, 1.9, 1.95)
+
+
+def _meq_of_input(fin):
+    """M f^eq(rho, j) of each input cell's own conserved moments."""
+    M = o3.tables()[0]
+    m = fin @ M.T
+    feq = o3.feq_field(m[:, 0], m[:, 1] / m[:, 0], m[:, 2] / m[:, 0], m[:, 3] / m[:, 0]).T
+    return m, feq, feq @ M.T
+
+
+def test_viscosity_ramp_at_zero_is_the_plain_scheme():
+    """The comparison strategy of Sec. 4.1 (non-conserved rates ramped
+    linearly to 1 across the layer) with the ramp coordinate 0 everywhere is
+    the undamped scheme bit for bit."""
+    f = random_state(6, 5, 4, 21, u0=(0.03, 0.0, -0.02))
+    a = o3.step(f, 6, s=S_RAMP, chi=0.0, variant="visc")
+    b = o3.step(f, 6, s=S_RAMP, chi=0.0, variant="none")
+    np.testing.assert_array_equal(a, b)
+
+
+def test_viscosity_ramp_at_one_lands_on_the_equilibrium():
+    """At ramp coordinate 1 every non-conserved rate is 1, so one collision
+    lands exactly on f^eq(rho, j) of the cell (the BGK s = 1 limit)."""
+    fin = random_state(4, 3, 2, 22, u0=(0.05, -0.03, 0.02)).reshape(15, -1).T
+    out = o3.collide(fin, s=S_RAMP, chi=1.0, variant="visc", qref=(1.3, 0.2, 0.1, 0.0))
+    _, feq, _ = _meq_of_input(fin)
+    np.testing.assert_allclose(out, feq, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("xi", [0.3, 0.75])
+def test_viscosity_ramp_relaxes_each_moment_at_the_ramped_rate(xi):
+    """In between, the conserved moments are kept (no force: q_ref and chi
+    play no part), and each non-conserved moment k moves from its value
+    towards m^eq_k by the ramped rate s'_k = s_k + (1 - s_k) xi:
+    m'_k - m^eq_k = (1 - s'_k)(m_k - m^eq_k)."""
+    fin = random_state(4, 3, 2, 23, u0=(-0.04, 0.02, 0.06)).reshape(15, -1).T
+    M = o3.tables()[0]
+    out = o3.collide(fin, s=S_RAMP, chi=xi, variant="visc", qref=(0.8, -0.1, 0.0, 0.2))
+    m_in, _, meq = _meq_of_input(fin)
+    m_out = out @ M.T
+    np.testing.assert_allclose(m_out[:, :4], m_in[:, :4], rtol=0, atol=1e-15)
+    for k in range(4, 15):
+        sk = S_RAMP[k] + (1 - S_RAMP[k]) * xi
+        np.testing.assert_allclose(m_out[:, k] - meq[:, k], (1 - sk) * (m_in[:, k] - meq[:, k]),
+                                   rtol=0, atol=1e-14)
+
+
+def test_viscosity_ramp_uniform_state_decay():
+    """A uniform state (wavenumber 0, streaming moves nothing) under a uniform
+    ramp coordinate: its conserved moments stay, so m^eq stays, and after T
+    steps each non-conserved moment's distance to m^eq has shrunk by
+    (1 - s'_k)^T."""
+    xi, T = 0.4, 5
+    base = o3.feq_field(np.full((2, 2, 2), 1.01), 0.04, -0.02, 0.03)
+    kick = np.random.default_rng(24).standard_normal(15) * 3e-3
+    f = base + kick[:, None, None, None]
+    g = o3.step(f, T, s=S_RAMP, chi=xi, variant="visc")
+    M = o3.tables()[0]
+    m0, _, meq = _meq_of_input(f[:, :1, :1, :1].reshape(15, 1).T)
+    m1 = g[:, :1, :1, :1].reshape(15, 1).T @ M.T
+    np.testing.assert_allclose(m1[0, :4], m0[0, :4], rtol=0, atol=1e-14)
+    for k in range(4, 15):
+        sk = S_RAMP[k] + (1 - S_RAMP[k]) * xi
+        np.testing.assert_allclose(m1[0, k] - meq[0, k], (1 - sk) ** T * (m0[0, k] - meq[0, k]),
+                                   rtol=0, atol=1e-14)

@@ -3,7 +3,9 @@
 Each case plants one mistake (a wrong coefficient, a dropped term, a flipped
 sign, a swapped index, a transposed operand) in a private copy of the C
 oracle, builds it with gcc and runs the pin suite against it; every mutant
-must make at least one pin fail. Nothing here touches the GPU.
+must make at least one pin fail (the short diagnostics pins run first, then
+the main pin suite, stopping at the first failure). Nothing here touches the
+GPU.
 """
 import os
 import subprocess
@@ -44,6 +46,13 @@ MUTANTS = {
     "source_velocity_dropped": ("feq(rs, rs * src[4], rs * src[5], fs);", "feq(rs, 0.0, 0.0, fs);"),
     "source_sine_sign": ("src[0] + src[1] * sin(", "src[0] - src[1] * sin("),
     "outflow_wrong_column": ("post[i * N + y * nx + nx - 1] = post[i * N + y * nx + nx - 2];", "post[i * N + y * nx + nx - 1] = post[i * N + y * nx + nx - 3];"),
+    "diag_base_without_velocity": ("feq(rho_b, rho_b * ux_b, rho_b * uy_b, fb);", "feq(rho_b, 0.0, 0.0, fb);"),
+    "diag_max_over_f": ("const double d = fabs(v - fb[i]);", "const double d = fabs(v);"),
+    "diag_jx_from_cy": ("      jx += CX[i] * v;", "      jx += CY[i] * v;"),
+    "diag_momentum_base_velocity": ("djx = jx - rho_b * ux_b", "djx = jx - ux_b"),
+    "diag_abs_not_square": ("s_r2 += dr * dr;", "s_r2 += fabs(dr);"),
+    "diag_max_includes_non_finite": ("    if (finite) {\n      if (dmax > mx) mx = dmax;",
+                                     "    if (dmax > mx) mx = dmax;\n    if (finite) {"),
 }
 
 
@@ -59,6 +68,7 @@ def test_pins_catch_mutant(name, tmp_path):
                            "-std=c99", "-o", str(so), str(mut), "-lm"])
     env = dict(os.environ, LBM_ORACLE_LIB=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_diag_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])

@@ -618,3 +618,4 @@ def test_line_source_emits_the_acoustic_wavelength(u0):
     x0 = down + seg[down] / (seg[down] - seg[down + 1])   # linear interpolation
     lam = np.diff(x0).mean()
     assert abs(lam / ((cs + u0) / 0.01) - 1) < 0.02, lam
+
