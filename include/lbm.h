@@ -145,12 +145,44 @@ int lbm_set_sponge_separable(lbm_handle *h, const double *chi_x,
  * without waiting. */
 int lbm_step(lbm_handle *h, int64_t n);
 
-/* Wait for all work of the handle. */
+/* Wait for all work of the handle. Returns LBM_EUNSTABLE once the
+ * instability detector (below) has tripped. */
 int lbm_sync(lbm_handle *h);
+
+/* ---- instability detector ---------------------------------------------
+ * Type I relaxes its non-conserved moments at the effective rate s + chi
+ * (Sec. 2.2.1, eq. effectrelax), so wherever s + chi > 2 the layer itself
+ * amplifies the solution (the Von Neumann threshold of Sec. 3.3), and a run
+ * past a stability limit grows until it overflows. The detector catches
+ * this during lbm_step: with every_n >= 1, after each kernel launch that
+ * brings the handle's step count to or past the next multiple of every_n,
+ * a check kernel reads the stored state on the handle's stream and trips if
+ * any cell holds a non-finite population or a deviation |f_i - f_i^base|
+ * larger than max_dev: the same condition as lbm_diagnostics reporting
+ * out[6] > 0 or out[5] > max_dev. (Launches of the K-step kernels advance K
+ * steps, so a check can land up to K - 1 steps after the multiple.) Batch
+ * ticks check their members the same way at the end of the tick. The first
+ * trip keeps the step count at which it was seen; from then on lbm_sync,
+ * lbm_moments and lbm_diagnostics complete their work (outputs written)
+ * and return LBM_EUNSTABLE, until the detector is set again or the state is
+ * replaced (lbm_set_populations, lbm_load_state, lbm_init_fields_dev).
+ *
+ * every_n: 0 switches the detector off (the default), otherwise the check
+ *          period in steps. max_dev: > 0, or +INFINITY to check for
+ *          non-finite values only. Errors: EINVAL (every_n < 0, max_dev
+ *          not > 0 or NaN), ENOMEM (the 8-byte device trip word).
+ *          Synchronises the handle's stream.
+ * Cost: one read of the nine planes per check (about one step's reads). */
+int lbm_set_detector(lbm_handle *h, int64_t every_n, double max_dev);
+
+/* Step count of the first trip, or -1 while the detector has not tripped
+ * (or is off). Synchronises; returns LBM_OK either way. */
+int lbm_detector_status(lbm_handle *h, int64_t *tripped_at);
 
 /* Raw pre-collision moments rho = sum_i f_i, u = sum_i c_i f_i / rho
  * (eq. q-macro) into host arrays [ny][nx] FP64 (any may be NULL).
- * Synchronises. */
+ * Synchronises; LBM_EUNSTABLE once the detector has tripped (the arrays
+ * are written all the same). */
 int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy);
 
 /* As lbm_moments into device arrays [ny][nx] FP64, asynchronous. */
@@ -160,10 +192,12 @@ int lbm_moments_dev(lbm_handle *h, double *rho, double *ux, double *uy);
  * deviations taken from the base state:
  *   out[0] = sum drho, out[1] = sum djx, out[2] = sum djy,
  *   out[3] = sum drho^2, out[4] = sum |dj|^2,
- *   out[5] = max_i,x |f_i - f_i^base|, out[6] = number of cells holding a
- *   non-finite population.
+ *   out[5] = max over the finite cells of max_i |f_i - f_i^base| (0 when no
+ *   cell is finite), out[6] = number of cells holding a non-finite
+ *   population (a non-finite cell also makes the sums non-finite).
  * E_L2 of Section 4.1 with rho_ref = rho_base is sqrt(out[3] / sum rho_ref^2).
- * Deterministic (fixed reduction order). Synchronises. */
+ * Deterministic (fixed reduction order). Synchronises; LBM_EUNSTABLE once
+ * the detector has tripped (out is written all the same). */
 int lbm_diagnostics(lbm_handle *h, double out[7]);
 
 /* As lbm_diagnostics into a device array of 7 doubles, asynchronous on the
@@ -330,7 +364,16 @@ int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t);
  * strip-kernel workgroups resident on the device at once; 0: always. */
 int lbm_batch_set_min_items(lbm_batch *b, int32_t min_items);
 
+/* Wait for the batch's work. Returns LBM_EUNSTABLE when the detector of a
+ * member (set with lbm_set_detector before the tick) has tripped; which
+ * ones and when is given by lbm_batch_detector_status. */
 int lbm_batch_sync(lbm_batch *b);
+
+/* Per member (in member-list order): the step count of its detector's first
+ * trip, or -1 (not tripped, or no detector). tripped_at: host array of the
+ * member count. Synchronises; returns LBM_OK either way. */
+int lbm_batch_detector_status(lbm_batch *b, int64_t *tripped_at);
+
 void lbm_batch_destroy(lbm_batch *b);
 
 /* ---- Von Neumann analysis (Section 3.2, eqs. eq:linearized, sec:matrix) --

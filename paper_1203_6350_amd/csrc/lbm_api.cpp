@@ -86,6 +86,12 @@ struct lbm_handle {
   int64_t steps = 0;
   size_t lat_bytes = 0;
   int device = 0;
+  // instability detector (lbm_set_detector)
+  int64_t det_every = 0;      // 0: off
+  double det_max = 0.0;
+  int64_t det_next = 0;       // step count at which the next check is due
+  unsigned long long *det_word = nullptr;  // device: first tripping step, or TRIP_NONE
+  int64_t tripped_at = -1;    // host copy of the trip, once read
 };
 
 namespace {
@@ -214,6 +220,46 @@ int ensure_diag(lbm_handle *h) {
           "hipMallocAsync(diagnostics)");
   HIP_TRY(hipMallocAsync((void **)&h->diag_out, 8 * sizeof(double), h->stream),
           "hipMallocAsync(diagnostics)");
+  return LBM_OK;
+}
+
+// Enqueue a detector check of the current lattice at the handle's step
+// count when one is due (called after every launch that advances it).
+int detector_after_launch(lbm_handle *h, hipStream_t stream, unsigned long long *trip2) {
+  if (!h->det_every || h->steps < h->det_next) return LBM_OK;
+  lbm::CheckDesc d;
+  lbm::fill_check_desc(h->cfg, h->lat[h->cur], d);
+  d.trip = h->det_word;
+  d.trip2 = trip2;
+  d.step = (unsigned long long)h->steps;
+  d.max_dev = h->det_max;
+  h->det_next = (h->steps / h->det_every + 1) * h->det_every;
+  HIP_TRY(lbm::launch_check(h->user.storage, d, stream), "detector kernel");
+  return LBM_OK;
+}
+
+// Forget any trip (new state or new settings); stream-ordered.
+int detector_reset(lbm_handle *h) {
+  h->tripped_at = -1;
+  if (h->det_every) h->det_next = (h->steps / h->det_every + 1) * h->det_every;
+  if (h->det_word)
+    HIP_TRY(lbm::launch_fill_u64(h->det_word, 1, lbm::TRIP_NONE, h->stream), "detector reset");
+  return LBM_OK;
+}
+
+// After the handle's stream has drained: fold the device trip word into the
+// host copy and report it.
+int detector_result(lbm_handle *h) {
+  if (!h->det_word) return LBM_OK;
+  unsigned long long w = lbm::TRIP_NONE;
+  HIP_TRY(hipMemcpyAsync(&w, h->det_word, sizeof(w), hipMemcpyDeviceToHost, h->stream),
+          "hipMemcpy(detector)");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (w != lbm::TRIP_NONE && (h->tripped_at < 0 || (int64_t)w < h->tripped_at))
+    h->tripped_at = (int64_t)w;
+  if (h->tripped_at >= 0)
+    return fail(LBM_EUNSTABLE, "instability detector tripped at step " +
+                                   std::to_string(h->tripped_at));
   return LBM_OK;
 }
 
@@ -449,6 +495,8 @@ int lbm_step(lbm_handle *h, int64_t n) {
         h->cfg.qfield = h->qf;
         h->cfg.qfield_out = h->qf2;
       }
+      int rc = detector_after_launch(h, h->stream, nullptr);
+      if (rc) return rc;
     }
   }
   for (; k < n; ++k) {
@@ -457,14 +505,42 @@ int lbm_step(lbm_handle *h, int64_t n) {
     if (e != hipSuccess) return hip_fail(e, "step kernel");
     h->cur = 1 - h->cur;
     h->steps += 1;
+    int rc = detector_after_launch(h, h->stream, nullptr);
+    if (rc) return rc;
   }
+  return LBM_OK;
+}
+
+int lbm_set_detector(lbm_handle *h, int64_t every_n, double max_dev) {
+  // arguments first, so that their checks need no device
+  if (every_n < 0) return fail(LBM_EINVAL, "every_n must be >= 0");
+  if (every_n > 0 && !(max_dev > 0.0)) return fail(LBM_EINVAL, "max_dev must be > 0 (may be infinite)");
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (every_n > 0 && !h->det_word)
+    HIP_TRY(hipMallocAsync((void **)&h->det_word, sizeof(unsigned long long), h->stream),
+            "hipMallocAsync(detector)");
+  h->det_every = every_n;
+  h->det_max = every_n > 0 ? max_dev : 0.0;
+  int rc = detector_reset(h);
+  if (rc) return rc;
+  // the word is now ready for any stream (a batch checks on its own)
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_detector_status(lbm_handle *h, int64_t *tripped_at) {
+  if (!h || !tripped_at) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  const int rc = detector_result(h);
+  if (rc != LBM_OK && rc != LBM_EUNSTABLE) return rc;
+  *tripped_at = h->tripped_at;
   return LBM_OK;
 }
 
 int lbm_sync(lbm_handle *h) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-  return LBM_OK;
+  return detector_result(h);
 }
 
 int lbm_moments_dev(lbm_handle *h, double *rho, double *ux, double *uy) {
@@ -486,7 +562,7 @@ int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy) {
   (void)hipFreeAsync(d, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(e, "moments");
-  return LBM_OK;
+  return detector_result(h);
 }
 
 int lbm_diagnostics(lbm_handle *h, double out[7]) {
@@ -499,7 +575,7 @@ int lbm_diagnostics(lbm_handle *h, double out[7]) {
     e = hipMemcpyAsync(out, h->diag_out, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
-  return LBM_OK;
+  return detector_result(h);
 }
 
 int lbm_diagnostics_dev(lbm_handle *h, double *out7_dev) {
@@ -539,7 +615,7 @@ int lbm_set_populations(lbm_handle *h, const double *f) {
   if (e != hipSuccess) return hip_fail(e, "set_populations");
   h->cur = 0;
   h->steps = 0;
-  return LBM_OK;
+  return detector_reset(h);
 }
 
 int lbm_state_bytes(lbm_handle *h, size_t *bytes) {
@@ -564,7 +640,7 @@ int lbm_load_state(lbm_handle *h, const void *host, size_t bytes) {
   HIP_TRY(hipMemcpy(h->lat[0], host, h->lat_bytes, hipMemcpyHostToDevice), "hipMemcpy(state)");
   h->cur = 0;
   std::memcpy(&h->steps, (const char *)host + h->lat_bytes, sizeof(int64_t));
-  return LBM_OK;
+  return detector_reset(h);
 }
 
 int lbm_get_info(lbm_handle *h, lbm_info *info) {
@@ -706,6 +782,7 @@ void lbm_destroy(lbm_handle *h) {
   if (h->qf2) (void)hipFreeAsync(h->qf2, h->stream);
   if (h->diag_partials) (void)hipFreeAsync(h->diag_partials, h->stream);
   if (h->diag_out) (void)hipFreeAsync(h->diag_out, h->stream);
+  if (h->det_word) (void)hipFreeAsync(h->det_word, h->stream);
   if (h->own_lat) {
     (void)hipStreamSynchronize(h->stream);
     for (int k = 0; k < 2; ++k)
@@ -825,7 +902,7 @@ int lbm_init_fields_dev(lbm_handle *h, const double *rho, const double *ux,
   if (e != hipSuccess) return hip_fail(e, "init kernel");
   h->cur = 0;
   h->steps = 0;
-  return LBM_OK;
+  return detector_reset(h);
 }
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
@@ -858,6 +935,14 @@ struct lbm_batch {
   int nitems = 0;
   size_t item_cap = 0;
   bool multi_def = false;  // every member takes the default form of the collision
+  // instability detector: per-member trip slots (one copy at lbm_batch_sync)
+  // and the descriptors of one tick's checks, staged like the members'
+  unsigned long long *d_trip = nullptr;            // [dom_cap]
+  lbm::CheckDesc *d_chk = nullptr;                 // [dom_cap]
+  lbm::CheckDesc *h_chk[2] = {nullptr, nullptr};   // pinned staging, alternating
+  hipEvent_t chk_copied[2] = {nullptr, nullptr};
+  int chk_slot = 0;
+  bool any_detector = false;  // some check ran since the member list was set
   // graphs keyed by (K or 0, K-step launches or ticks, remainder launches,
   // tile workgroups per CU, strip workgroup waves, default form)
   std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
@@ -955,9 +1040,13 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->d_ntiles) (void)hipFree(b->d_ntiles);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_nitems) (void)hipFree(b->d_nitems);
+  if (b->d_trip) (void)hipFree(b->d_trip);
+  if (b->d_chk) (void)hipFree(b->d_chk);
   for (int k = 0; k < 2; ++k) {
     if (b->h_doms[k]) (void)hipHostFree(b->h_doms[k]);
     if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+    if (b->h_chk[k]) (void)hipHostFree(b->h_chk[k]);
+    if (b->chk_copied[k]) (void)hipEventDestroy(b->chk_copied[k]);
   }
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -1054,18 +1143,29 @@ int batch_set_members_impl(lbm_batch *b, lbm_handle *const *members, int32_t cou
     free_graphs(b);
     if (b->d_doms) (void)hipFree(b->d_doms);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
-    for (int k = 0; k < 2; ++k)
+    if (b->d_trip) (void)hipFree(b->d_trip);
+    if (b->d_chk) (void)hipFree(b->d_chk);
+    for (int k = 0; k < 2; ++k) {
       if (b->h_doms[k]) (void)hipHostFree(b->h_doms[k]);
+      if (b->h_chk[k]) (void)hipHostFree(b->h_chk[k]);
+    }
     b->d_doms = nullptr;
     b->d_tiles = nullptr;
+    b->d_trip = nullptr;
+    b->d_chk = nullptr;
     b->h_doms[0] = b->h_doms[1] = nullptr;
+    b->h_chk[0] = b->h_chk[1] = nullptr;
     b->dom_cap = b->tile_cap = 0;
     const size_t dc = std::max<size_t>((size_t)count, 2 * b->members.size());
     const size_t tc = std::max<size_t>(tiles.size(), (size_t)(1.5 * tiles.size()));
     hipError_t e = hipMalloc((void **)&b->d_doms, sizeof(lbm::BatchDomain) * dc);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sizeof(int2) * tc);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_trip, sizeof(unsigned long long) * dc);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_chk, sizeof(lbm::CheckDesc) * dc);
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
       e = hipHostMalloc((void **)&b->h_doms[k], sizeof(lbm::BatchDomain) * dc, hipHostMallocDefault);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+      e = hipHostMalloc((void **)&b->h_chk[k], sizeof(lbm::CheckDesc) * dc, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "batch buffers");
     b->dom_cap = dc;
     b->tile_cap = tc;
@@ -1076,7 +1176,47 @@ int batch_set_members_impl(lbm_batch *b, lbm_handle *const *members, int32_t cou
   HIP_TRY(hipMemcpy(b->d_ntiles, &b->ntiles, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy(ntiles)");
   b->members.assign(members, members + count);
   b->storage = members[0]->user.storage;
+  // fresh trip slots for the new member list
+  HIP_TRY(lbm::launch_fill_u64(b->d_trip, count, lbm::TRIP_NONE, b->stream), "detector slots");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  b->any_detector = false;
   return build_items(b);
+}
+
+// After a tick: one launch checks every member whose detector is due at
+// its new step count (its own trip word and the batch's slot).
+int batch_detector_checks(lbm_batch *b) {
+  const int sl = b->chk_slot;
+  lbm::CheckDesc *hc = b->h_chk[sl];
+  int nd = 0;
+  int64_t max_cells = 0;
+  bool waited = false;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    lbm_handle *h = b->members[i];
+    if (!h->det_every || h->steps < h->det_next) continue;
+    if (!waited) {  // the copy that last read this staging buffer has finished
+      HIP_TRY(hipEventSynchronize(b->chk_copied[sl]), "hipEventSynchronize");
+      waited = true;
+    }
+    lbm::CheckDesc &d = hc[nd++];
+    lbm::fill_check_desc(h->cfg, h->lat[h->cur], d);
+    d.trip = h->det_word;
+    d.trip2 = b->d_trip + i;
+    d.step = (unsigned long long)h->steps;
+    d.max_dev = h->det_max;
+    h->det_next = (h->steps / h->det_every + 1) * h->det_every;
+    max_cells = std::max(max_cells, d.n);
+  }
+  if (!nd) return LBM_OK;
+  b->chk_slot ^= 1;
+  b->any_detector = true;
+  HIP_TRY(hipMemcpyAsync(b->d_chk, hc, sizeof(lbm::CheckDesc) * nd, hipMemcpyHostToDevice,
+                         b->stream), "hipMemcpy(detector descriptors)");
+  HIP_TRY(hipEventRecord(b->chk_copied[sl], b->stream), "hipEventRecord");
+  for (int off = 0; off < nd; off += 65535)
+    HIP_TRY(lbm::launch_check_batch(b->storage, b->d_chk + off, std::min(65535, nd - off),
+                                    max_cells, b->stream), "detector kernel");
+  return LBM_OK;
 }
 
 }  // namespace
@@ -1108,6 +1248,8 @@ int lbm_batch_create(lbm_handle *const *members, int32_t count, void *stream,
   b->multi_k = b->storage == LBM_STORAGE_F32 ? 4 : 3;
   for (int k = 0; k < 2 && e == hipSuccess; ++k)
     e = hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&b->chk_copied[k], hipEventDisableTiming);
   if (e != hipSuccess) {
     lbm_batch_destroy(b);
     return hip_fail(e, "lbm_batch_create");
@@ -1217,7 +1359,7 @@ int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
     b->members[i]->cur ^= launches & 1;
     b->members[i]->steps += st;
   }
-  return LBM_OK;
+  return batch_detector_checks(b);
 }
 
 int lbm_batch_step(lbm_batch *b, int64_t n) {
@@ -1233,9 +1375,45 @@ int lbm_batch_step(lbm_batch *b, int64_t n) {
   return LBM_OK;
 }
 
+namespace {
+// Fold the batch's trip slots into the members' host copies; the batch
+// stream must be idle. Returns the number of members that have tripped.
+int batch_fold_trips(lbm_batch *b, int *tripped) {
+  *tripped = 0;
+  if (b->any_detector) {
+    std::vector<unsigned long long> w(b->members.size());
+    HIP_TRY(hipMemcpy(w.data(), b->d_trip, sizeof(unsigned long long) * w.size(),
+                      hipMemcpyDeviceToHost), "hipMemcpy(detector slots)");
+    for (size_t i = 0; i < w.size(); ++i) {
+      lbm_handle *h = b->members[i];
+      if (w[i] != lbm::TRIP_NONE && (h->tripped_at < 0 || (int64_t)w[i] < h->tripped_at))
+        h->tripped_at = (int64_t)w[i];
+    }
+  }
+  for (const lbm_handle *h : b->members) *tripped += h->det_every && h->tripped_at >= 0;
+  return LBM_OK;
+}
+}  // namespace
+
 int lbm_batch_sync(lbm_batch *b) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  int tripped = 0;
+  int rc = batch_fold_trips(b, &tripped);
+  if (rc) return rc;
+  if (tripped)
+    return fail(LBM_EUNSTABLE, std::to_string(tripped) + " member(s) tripped the instability detector");
+  return LBM_OK;
+}
+
+int lbm_batch_detector_status(lbm_batch *b, int64_t *tripped_at) {
+  if (!b || !tripped_at) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  int tripped = 0;
+  int rc = batch_fold_trips(b, &tripped);
+  if (rc) return rc;
+  for (size_t i = 0; i < b->members.size(); ++i)
+    tripped_at[i] = b->members[i]->det_every ? b->members[i]->tripped_at : -1;
   return LBM_OK;
 }
 

@@ -113,6 +113,30 @@ hipError_t launch_diagnostics(const StepConfig &c, const void *src,
                               hipStream_t stream);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,
                        hipStream_t stream);
+
+// Instability detector: scans the nine stored planes of one lattice and, if
+// any deviation is non-finite or larger than max_dev in magnitude, lowers
+// *trip (and *trip2 when not NULL) to `step` (atomic minimum; "not tripped"
+// is ~0ull).
+struct CheckDesc {
+  const void *lat;
+  unsigned long long *trip;
+  unsigned long long *trip2;
+  int64_t n;               // cells per plane (nx * ny; rows are contiguous)
+  int64_t ps;              // elements between planes
+  unsigned long long step;
+  double max_dev;
+  double scale[9];         // storage scale of each plane (FP16 mode)
+};
+constexpr unsigned long long TRIP_NONE = ~0ull;
+void fill_check_desc(const StepConfig &c, const void *lat, CheckDesc &d);
+hipError_t launch_check(int storage, const CheckDesc &d, hipStream_t stream);
+// descs_dev: device array of ndesc descriptors (one member each); max_cells:
+// the largest n among them.
+hipError_t launch_check_batch(int storage, const CheckDesc *descs_dev, int ndesc,
+                              int64_t max_cells, hipStream_t stream);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
+                           hipStream_t stream);
 int elem_bytes_of(int storage);
 
 // Batched stepping (lbm_batch.hip). One descriptor per member domain.

@@ -640,7 +640,9 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_kernel(
     acc[2] += djy;
     acc[3] += dr * dr;
     acc[4] += djx * djx + djy * djy;
-    acc[5] = fmax(acc[5], mx);
+    // the largest deviation is taken over the finite cells; non-finite
+    // cells are counted instead
+    if (finite) acc[5] = fmax(acc[5], mx);
     acc[6] += finite ? 0.0 : 1.0;
   }
   __shared__ double red[DIAG_THREADS / 64][7];
@@ -747,6 +749,94 @@ hipError_t launch_diagnostics(const StepConfig &c, const void *src,
   });
   if (e != hipSuccess) return e;
   diag_final_kernel<<<1, 64, 0, stream>>>(partials, out7);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- detector
+// Trips when any stored deviation is non-finite or exceeds max_dev in
+// magnitude: every element of the nine planes is one of the cells'
+// pre-collision deviations (the pull layout permutes them), so this is
+// exactly "non-finite count > 0 or max |f - f^base| over finite cells >
+// max_dev" of the diagnostics. The planes are streamed linearly (coalesced);
+// a block that finds a tripping element lowers the trip word(s) to the step
+// count with one atomic minimum.
+template <typename S>
+__device__ __forceinline__ bool check_planes(const CheckDesc &d, int64_t t, int64_t nt) {
+  bool bad = false;
+  const S *base = (const S *)d.lat;
+#pragma unroll 1
+  for (int i = 0; i < 9; ++i) {
+    const S *p = base + (int64_t)i * d.ps;
+    const double sc = d.scale[i];
+    for (int64_t c = t; c < d.n; c += nt) bad |= !(fabs(load_dev<S>(p + c, sc)) <= d.max_dev);
+  }
+  return bad;
+}
+
+__device__ __forceinline__ void check_report(const CheckDesc &d, bool bad) {
+  if (__syncthreads_or(bad) && threadIdx.x == 0) {
+    atomicMin(d.trip, d.step);
+    if (d.trip2) atomicMin(d.trip2, d.step);
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void check_kernel(CheckDesc d) {
+  const bool bad = check_planes<S>(d, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                                   (int64_t)gridDim.x * 256);
+  check_report(d, bad);
+}
+
+// Batch form: blockIdx.y selects the member's descriptor.
+template <typename S>
+__global__ __launch_bounds__(256) void check_batch_kernel(const CheckDesc *__restrict__ ds) {
+  const CheckDesc d = ds[blockIdx.y];
+  const bool bad = check_planes<S>(d, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                                   (int64_t)gridDim.x * 256);
+  check_report(d, bad);
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void fill_check_desc(const StepConfig &c, const void *lat, CheckDesc &d) {
+  d.lat = lat;
+  d.n = (int64_t)c.nx * c.ny;  // pitch == nx: the cells of a plane are contiguous
+  d.ps = c.plane_stride;
+  for (int i = 0; i < 9; ++i) d.scale[i] = storage_scale(c, i);
+}
+
+static unsigned check_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+hipError_t launch_check(int storage, const CheckDesc &d, hipStream_t stream) {
+  return by_storage(storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    check_kernel<S><<<check_blocks(d.n), 256, 0, stream>>>(d);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_check_batch(int storage, const CheckDesc *descs_dev, int ndesc,
+                              int64_t max_cells, hipStream_t stream) {
+  if (ndesc < 1) return hipSuccess;
+  if (ndesc > 65535) return hipErrorInvalidValue;
+  const unsigned bx = check_blocks(max_cells) < 64 ? check_blocks(max_cells) : 64;
+  return by_storage(storage, [&](auto tag) {
+    typedef std::remove_pointer_t<decltype(tag)> S;
+    check_batch_kernel<S><<<dim3(bx, (unsigned)ndesc), 256, 0, stream>>>(descs_dev);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
+                           hipStream_t stream) {
+  if (n < 1) return hipSuccess;
+  fill_u64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(p, n, v);
   return hipGetLastError();
 }
 

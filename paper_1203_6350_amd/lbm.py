@@ -28,6 +28,15 @@ class LbmError(RuntimeError):
         self.code = code
 
 
+class LbmUnstable(LbmError):
+    """LBM_EUNSTABLE: the instability detector has tripped. The call still
+    completed; ``result`` holds what it returns otherwise (or None)."""
+
+    def __init__(self, code, msg, result=None):
+        super().__init__(code, msg)
+        self.result = result
+
+
 class lbm_config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("rho_base", ctypes.c_double), ("ux_base", ctypes.c_double),
@@ -144,6 +153,9 @@ def load(path: str | None = None):
         "lbm_batch_set_members": [_H, ctypes.POINTER(_H), i32],
         "lbm_init_fields_dev": [_H, vp, vp, vp],
         "lbm_batch_sync": [_H],
+        "lbm_set_detector": [_H, i64, ctypes.c_double],
+        "lbm_detector_status": [_H, ctypes.POINTER(i64)],
+        "lbm_batch_detector_status": [_H, ctypes.POINTER(i64)],
         "lbm3_create": [ctypes.POINTER(lbm3_config), _DP, _DP, _DP, _DP, ctypes.POINTER(_H)],
         "lbm3_set_sponge": [_H, _DP, ctypes.POINTER(lbm3_qref)],
         "lbm3_set_sponge_separable": [_H, _DP, _DP, _DP, i32, ctypes.POINTER(lbm3_qref)],
@@ -173,10 +185,13 @@ def load(path: str | None = None):
     return L
 
 
-def _check(rc):
+def _check(rc, result=None):
     if rc != LBM_OK:
         msg = load().lbm_last_error()
-        raise LbmError(rc, msg.decode() if msg else "")
+        msg = msg.decode() if msg else ""
+        if rc == LBM_EUNSTABLE:
+            raise LbmUnstable(rc, msg, result)
+        raise LbmError(rc, msg)
 
 
 def _host(a, n=None):
@@ -324,7 +339,7 @@ def lbm_moments(h):
     shape = (info.ny, info.nx)
     rho, ux, uy = (np.empty(shape) for _ in range(3))
     _check(load().lbm_moments(h, rho.ctypes.data_as(_DP), ux.ctypes.data_as(_DP),
-                              uy.ctypes.data_as(_DP)))
+                              uy.ctypes.data_as(_DP)), (rho, ux, uy))
     return rho, ux, uy
 
 
@@ -334,8 +349,21 @@ def lbm_moments_dev(h, rho, ux, uy):
 
 def lbm_diagnostics(h):
     out = np.empty(7)
-    _check(load().lbm_diagnostics(h, out.ctypes.data_as(_DP)))
+    _check(load().lbm_diagnostics(h, out.ctypes.data_as(_DP)), out)
     return out
+
+
+def lbm_set_detector(h, every_n, max_dev=float("inf")):
+    """Instability detector: check every ``every_n`` steps (0: off) for
+    non-finite populations or deviations above ``max_dev``."""
+    _check(load().lbm_set_detector(h, int(every_n), float(max_dev)))
+
+
+def lbm_detector_status(h):
+    """Step count of the detector's first trip, or -1."""
+    t = ctypes.c_int64(-1)
+    _check(load().lbm_detector_status(h, ctypes.byref(t)))
+    return int(t.value)
 
 
 def lbm_diagnostics_dev(h, out7):
@@ -485,6 +513,12 @@ class Lattice:
     def diagnostics(self):
         return lbm_diagnostics(self.h)
 
+    def set_detector(self, every_n, max_dev=float("inf")):
+        lbm_set_detector(self.h, every_n, max_dev)
+
+    def detector_status(self):
+        return lbm_detector_status(self.h)
+
     def populations(self):
         return lbm_get_populations(self.h)
 
@@ -580,6 +614,13 @@ def lbm_batch_sync(b):
     _check(load().lbm_batch_sync(b))
 
 
+def lbm_batch_detector_status(b, count):
+    """Per member: step count of its detector's first trip, or -1."""
+    out = np.empty(count, dtype=np.int64)
+    _check(load().lbm_batch_detector_status(b, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
 def lbm_batch_destroy(b):
     if b is not None:
         load().lbm_batch_destroy(b)
@@ -619,6 +660,9 @@ class Batch:
 
     def sync(self):
         lbm_batch_sync(self.b)
+
+    def detector_status(self):
+        return lbm_batch_detector_status(self.b, len(self.members))
 
     def close(self):
         if self.b is not None:

@@ -142,3 +142,33 @@ def test_sponge_generators():
     assert s[W] == 0.0
     two = wl.sponge_2d(r, r)
     assert two.shape == (64, 64) and two[0, 30] == pytest.approx(0.2) and two[30, 30] == 0
+
+
+@pytest.mark.parametrize("every_n,max_dev,msg", [
+    (-1, 1.0, "every_n"), (10, 0.0, "max_dev"), (10, -1.0, "max_dev"),
+    (10, float("nan"), "max_dev"), (10, 1.0, "handle"), (0, float("nan"), "handle"),
+])
+def test_detector_rejects_bad_arguments(every_n, max_dev, msg):
+    """lbm_set_detector checks its arguments before the handle: a negative
+    period or a max_dev that is not > 0 (NaN included) is EINVAL; with good
+    arguments a NULL handle is EINVAL; every_n = 0 (off) ignores max_dev."""
+    L = lbm.load()
+    assert L.lbm_set_detector(None, every_n, max_dev) == lbm.LBM_EINVAL
+    assert msg in lbm.lbm_last_error()
+
+
+def test_detector_status_null_arguments():
+    L = lbm.load()
+    t = ctypes.c_int64(0)
+    assert L.lbm_detector_status(None, ctypes.byref(t)) == lbm.LBM_EINVAL
+    assert L.lbm_batch_detector_status(None, ctypes.byref(t)) == lbm.LBM_EINVAL
+    assert L.lbm_batch_sync(None) == lbm.LBM_EINVAL
+
+
+def test_unstable_error_carries_the_result():
+    """The binding raises LbmUnstable (an LbmError) for LBM_EUNSTABLE and
+    keeps the outputs the call wrote."""
+    with pytest.raises(lbm.LbmError) as e:
+        lbm._check(lbm.LBM_EUNSTABLE, result=np.arange(7.0))
+    assert isinstance(e.value, lbm.LbmUnstable) and e.value.code == lbm.LBM_EUNSTABLE
+    np.testing.assert_array_equal(e.value.result, np.arange(7.0))
