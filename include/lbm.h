@@ -204,6 +204,20 @@ int lbm_diagnostics(lbm_handle *h, double out[7]);
  * handle's stream. */
 int lbm_diagnostics_dev(lbm_handle *h, double *out7_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lbm_diagnostics_dev without any allocation. lbm_diagnostics_dev
+ * allocates its per-block partials (56 KiB) at its first call on a handle;
+ * this variant takes them from a static device array of that fixed size
+ * instead (one per device, held until the process ends, its address looked
+ * up at the first call on each device). Same kernels and results, bit for
+ * bit. Every call on one device shares that array: calls that overlap on
+ * one device (different streams, or different host threads) race and must
+ * be ordered by the caller. Errors: EINVAL (NULL argument, or a reduction
+ * whose partials would exceed the array's size), EDEVICE. Asynchronous;
+ * does not report the detector. */
+int lbm_diagnostics_dev_noalloc(lbm_handle *h, double *out7_dev);
+
 /* Full pre-collision populations f = f^base + g in FP64, host [9][ny][nx].
  * Synchronises. */
 int lbm_get_populations(lbm_handle *h, double *f);

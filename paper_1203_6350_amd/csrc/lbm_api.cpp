@@ -588,6 +588,20 @@ int lbm_diagnostics_dev(lbm_handle *h, double *out7_dev) {
   return LBM_OK;
 }
 
+int lbm_diagnostics_dev_noalloc(lbm_handle *h, double *out7_dev) {
+  if (!h || !out7_dev) return fail(LBM_EINVAL, "NULL argument");
+  double *ws = nullptr;
+  size_t ws_bytes = 0;
+  HIP_TRY(lbm::diag_scratch(h->device, &ws, &ws_bytes), "diagnostics workspace");
+  if (lbm::diag_partials_bytes(h->cfg) > ws_bytes)
+    return fail(LBM_EINVAL, "the reduction needs " + std::to_string(lbm::diag_partials_bytes(h->cfg)) +
+                                " bytes of partials, above the static workspace of " +
+                                std::to_string(ws_bytes));
+  hipError_t e = lbm::launch_diagnostics(h->cfg, h->lat[h->cur], ws, out7_dev, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics");
+  return LBM_OK;
+}
+
 int lbm_get_populations(lbm_handle *h, double *f) {
   if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
   const int64_t N = h->user.nx * h->user.ny;

@@ -108,6 +108,9 @@ hipError_t launch_moments(const StepConfig &c, const void *src, double *rho,
 // partials: device scratch of at least diag_partials_bytes(c) bytes;
 // out7: device array of 7 doubles.
 size_t diag_partials_bytes(const StepConfig &c);
+// Device address and size of the static partials workspace of the
+// allocation-free diagnostics call on `device` (looked up once per device).
+hipError_t diag_scratch(int device, double **ptr, size_t *bytes);
 hipError_t launch_diagnostics(const StepConfig &c, const void *src,
                               double *partials, double *out7,
                               hipStream_t stream);

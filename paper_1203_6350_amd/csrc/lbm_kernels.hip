@@ -10,6 +10,7 @@
 // coalesced and the reads of the six x-shifted planes are offset by one
 // element.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "lbm_device.h"
@@ -680,6 +681,40 @@ __global__ __launch_bounds__(64) void diag_final_kernel(
 
 size_t diag_partials_bytes(const StepConfig &) {
   return sizeof(double) * 7 * DIAG_BLOCKS;
+}
+
+// Workspace of the allocation-free diagnostics call: the per-block partials
+// of one reduction (56 KiB). Each device holds its own copy until the
+// process ends; every call on a device shares it, so calls that overlap on
+// one device race. Host code never passes the array's name to a kernel: it
+// takes the device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[7 * DIAG_BLOCKS];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+
+hipError_t diag_scratch(int device, double **ptr, size_t *bytes) {
+  static std::mutex mu;
+  static void *addr[SCRATCH_MAX_DEVICES] = {};
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = (double *)addr[device];
+  *bytes = sizeof(scratch);
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- launchers

@@ -127,6 +127,7 @@ def load(path: str | None = None):
         "lbm_moments_dev": [_H, vp, vp, vp],
         "lbm_diagnostics": [_H, _DP],
         "lbm_diagnostics_dev": [_H, vp],
+        "lbm_diagnostics_dev_noalloc": [_H, vp],
         "lbm_get_populations": [_H, _DP],
         "lbm_set_populations": [_H, _DP],
         "lbm_get_info": [_H, ctypes.POINTER(lbm_info)],
@@ -368,6 +369,12 @@ def lbm_detector_status(h):
 
 def lbm_diagnostics_dev(h, out7):
     _check(load().lbm_diagnostics_dev(h, _dev(out7)))
+
+
+def lbm_diagnostics_dev_noalloc(h, out7):
+    """lbm_diagnostics_dev with its partials in the library's static device
+    workspace (no allocation; overlapping calls on one device race)."""
+    _check(load().lbm_diagnostics_dev_noalloc(h, _dev(out7)))
 
 
 def lbm_get_populations(h):
