@@ -279,13 +279,19 @@ def characteristics(rho, ux, rho0, u0, lo, hi):
     return 0.5 * (p + rho0 * cs * u), 0.5 * (p - rho0 * cs * u)
 
 
-def precision_leg(lbm, wl, n=2048, steps=4000, chis=(0.05, 0.2, 0.5), width=48):
+PRECISION_CHIS = (0.05, 0.2, 0.5)
+
+
+def precision_leg(lbm, wl, n=2048, steps=4000, chis=PRECISION_CHIS, width=48, reference=None):
     """Plane packet (amplitude 1e-4, wavelength 64, 8 wavelengths) in Mach-0.1
     flow entering a 48-cell x-sponge, Type II. Each storage mode and base on
-    the n x n lattice against the library's FP64 run (reference base) of the
-    n x 1 lattice: a y-uniform state with an x-only sponge evolves row by row
-    like the one-row lattice. The test suite holds that FP64 run to the
-    oracle (populations within 1e-12 of max |f| on this set-up)."""
+    the n x n lattice against a reference of the n x 1 row (a y-uniform state
+    with an x-only sponge evolves row by row like the one-row lattice): the
+    FP64 oracle's row (``reference``: chi_max -> (rho, u_x) after `steps`,
+    computed and timed by the CPU-baseline leg), or, when that leg is
+    skipped, the library's FP64 run of the row. Errors of p' relative to the
+    initial wave and to the current reference field; R and T (characteristic
+    split over the physical range, normalised by the incident wave)."""
     import numpy as np
     u0 = 0.1 * wl.CS
     rho, ux, uy = wl.plane_packet(n, n, amp=1e-4, wavelength=64.0, n_wavelengths=8,
@@ -294,18 +300,23 @@ def precision_leg(lbm, wl, n=2048, steps=4000, chis=(0.05, 0.2, 0.5), width=48):
     lo, hi = width, n - width
     p0p, _ = characteristics(rho[0], ux[0], 1.0, u0, lo, hi)
     norm0 = float(np.sqrt((p0p ** 2).sum()))
-    out = {}
+    out = {"reference": "oracle" if reference else "library FP64 one-row lattice"}
     for chi_max in chis:
         q = (1.0, u0, 0.0)
-        one = lbm.Lattice(n, 1, rho=rho[:1], ux=ux[:1], uy=uy[:1], storage="f64", variant="II",
-                          ux_base=u0)
-        one.set_sponge_separable(chi_max * cx, None, "max", q)
-        one.step(steps)
-        rr, ur, _ = one.moments()
-        one.close()
-        rp, rm = characteristics(rr[0], ur[0], 1.0, u0, lo, hi)
-        row = {"fp64_one_row_R": float(np.sqrt((rm ** 2).sum())) / norm0,
-               "fp64_one_row_T": float(np.sqrt((rp ** 2).sum())) / norm0}
+        if reference:
+            rr, ur = reference[chi_max]
+        else:
+            one = lbm.Lattice(n, 1, rho=rho[:1], ux=ux[:1], uy=uy[:1], storage="f64",
+                              variant="II", ux_base=u0)
+            one.set_sponge_separable(chi_max * cx, None, "max", q)
+            one.step(steps)
+            r1, u1, _ = one.moments()
+            one.close()
+            rr, ur = r1[0], u1[0]
+        rp, rm = characteristics(rr, ur, 1.0, u0, lo, hi)
+        R_ref = float(np.sqrt((rm ** 2).sum())) / norm0
+        T_ref = float(np.sqrt((rp ** 2).sum())) / norm0
+        row = {"reference_R": R_ref, "reference_T": T_ref}
         for storage in ("f64", "f32", "f16"):
             for base in ("rest", "ref"):
                 lat = lbm.Lattice(n, n, rho=rho, ux=ux, uy=uy, storage=storage, variant="II",
@@ -315,18 +326,18 @@ def precision_leg(lbm, wl, n=2048, steps=4000, chis=(0.05, 0.2, 0.5), width=48):
                 g_rho, g_ux, _ = lat.moments()
                 lat.close()
                 pr = g_rho - 1.0
-                pref = rr[0] - 1.0
+                pref = rr - 1.0
                 p_init = rho[0] - 1.0
                 sq = ((pr - pref[None, :]) ** 2).sum() / n
-                err = float(np.sqrt(sq / (pref ** 2).sum()))
-                err0 = float(np.sqrt(sq / (p_init ** 2).sum()))
-                rows_equal = bool((g_rho == g_rho[:1]).all())
                 gp, gm = characteristics(g_rho[0], g_ux[0], 1.0, u0, lo, hi)
+                R = float(np.sqrt((gm ** 2).sum())) / norm0
+                T = float(np.sqrt((gp ** 2).sum())) / norm0
                 row["%s_%s" % (storage, base)] = {
-                    "pprime_rel_l2": err, "pprime_err_over_initial": err0,
-                    "rows_identical": rows_equal,
-                    "R": float(np.sqrt((gm ** 2).sum())) / norm0,
-                    "T": float(np.sqrt((gp ** 2).sum())) / norm0}
+                    "pprime_rel_l2": float(np.sqrt(sq / (pref ** 2).sum())),
+                    "pprime_err_over_initial": float(np.sqrt(sq / (p_init ** 2).sum())),
+                    "rows_identical": bool((g_rho == g_rho[:1]).all()),
+                    "R": R, "T": T, "R_abs_err": abs(R - R_ref), "R_rel_err": abs(R - R_ref) / R_ref,
+                    "T_abs_err": abs(T - T_ref), "T_rel_err": abs(T - T_ref) / T_ref}
         out["chi_max=%g" % chi_max] = row
     return out
 
@@ -380,9 +391,13 @@ def _cpu_model():
 def cpu_baseline(spec, fields, steps, wl=None):
     """The FP64 oracle, as it stands, on bounded samples of the workloads: the
     headline (all host threads, and one thread for two steps), the 128^2
-    parity case, the 2048 x 1 row of the precision study and the smaller
-    batched domains."""
+    parity case, the 2048 x 1 row of the precision study for each chi_max
+    (whose final rows the precision leg then takes as its reference), the
+    smaller batched domains and the Von Neumann eigenvalues (LAPACK) of a
+    seeded sample of wavenumbers. Returns (summary, precision reference)."""
+    import numpy as np
     import oracle
+    import oracle.vn as ovn
     rho, ux, uy = fields
     threads = len(os.sched_getaffinity(0))
 
@@ -396,6 +411,7 @@ def cpu_baseline(spec, fields, steps, wl=None):
     dt = run(f0, steps, threads, **kw)
     dt1 = run(f0, 2, 1, **kw)
     del f0
+    prec_ref = {}
     out = {"value": spec.nx * spec.ny * steps / dt / 1e6, "unit": "MLUPS",
            "cores": threads, "kind": "oracle",
            "sample": "%dx%d workload, %d steps, Type %s, FP64, %.1f s" %
@@ -412,10 +428,19 @@ def cpu_baseline(spec, fields, steps, wl=None):
         n3, steps3 = 2048, 4000
         u0 = 0.1 * wl.CS
         r3, u3, v3 = wl.plane_packet(n3, 1, amp=1e-4, centre=n3 / 2, u0=u0)
-        cx = wl.quadratic_ramp_1d(n3, 48, 0.2)
-        t = run(oracle.feq_field(r3, u3, v3), steps3, 1, chi=cx[None, :], qref=(1.0, u0, 0.0),
-                variant="II")
-        out["c3_2048x1_row_4000_steps"] = {"mlups": n3 * steps3 / t / 1e6, "s": t}
+        f3 = oracle.feq_field(r3, u3, v3)
+        t3 = {}
+        for chi_max in PRECISION_CHIS:
+            cx = wl.quadratic_ramp_1d(n3, 48, chi_max)
+            t0 = time.perf_counter()
+            fT = oracle.step(f3, steps3, nthreads=1, chi=cx[None, :], qref=(1.0, u0, 0.0),
+                             variant="II")
+            t3["chi_max=%g" % chi_max] = time.perf_counter() - t0
+            rT, uT, _ = oracle.moments(fT)
+            prec_ref[chi_max] = (rT[0], uT[0])
+        t = sum(t3.values())
+        out["c3_2048x1_row_4000_steps"] = {"mlups": len(t3) * n3 * steps3 / t / 1e6, "s": t,
+                                           "runs": t3}
         small = [d for d in wl.batch_c4() if d.nx <= 256]
         cells, t = 0, 0.0
         for d in small:
@@ -425,7 +450,20 @@ def cpu_baseline(spec, fields, steps, wl=None):
             cells += d.nx * d.ny
         out["c4_domains_n_le_256_20_steps"] = {"domains": len(small), "mlups": cells * 20 / t / 1e6,
                                                "s": t}
-    return out
+        # Von Neumann: LAPACK eigenvalues of G(k) (numpy) on a seeded sample of
+        # 1024 wavenumbers of the 256^2 grid for each of the 64 parameter sets
+        kx, ky = wl.vn_grid(256)
+        pick = np.random.default_rng(12036353).choice(kx.size, 1024, replace=False)
+        sets = wl.vn_param_sets(64)
+        t0 = time.perf_counter()
+        for p in sets:
+            ovn.eigenvalues(p["s"], p["chi"], p["qref"], kx[pick], ky[pick], p.get("n", 0.5),
+                            p.get("m", 0.5), p["variant"])
+        tv = time.perf_counter() - t0
+        out["vn_lapack"] = {"kpoints": len(sets) * pick.size, "s": tv,
+                            "kpoints_per_s": len(sets) * pick.size / tv, "threads": 1,
+                            "sample": "64 parameter sets x 1024 seeded wavenumbers of the 256^2 grid"}
+    return out, prec_ref
 
 
 def qref_leg(lbm, wl, torch, n=4096, steps=400, warmup=20, alpha=1e-3):
@@ -706,18 +744,19 @@ def main():
     if not args.no_batch:
         print("bench: batched 256-domain leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(lbm, wl, torch)
+    prec_ref = None
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
+        out["cpu_baseline"], prec_ref = cpu_baseline(spec, fields, args.cpu_steps, wl)
     if not args.no_precision:
         print("bench: precision study 2048^2, 4000 steps", file=sys.stderr, flush=True)
-        out["precision"] = precision_leg(lbm, wl)
+        out["precision"] = precision_leg(lbm, wl, reference=prec_ref)
     if not args.no_pulse:
         print("bench: the paper's pulse comparison", file=sys.stderr, flush=True)
         out["paper_pulse"] = paper_pulse_leg(lbm, wl)
     if not args.no_serve:
         out["served"] = serving_leg(torch, count=args.serve_requests,
                                     warmup=args.serve_requests // 10)
-    if not args.no_cpu_baseline:
-        print("bench: CPU oracle baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(spec, fields, args.cpu_steps, wl)
     print(json.dumps(out), flush=True)
 
 

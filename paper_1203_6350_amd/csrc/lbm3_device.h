@@ -160,8 +160,9 @@ __device__ __forceinline__ void collide3(C g[15], C chi, const CollideParams3<C>
   }
 
   // ---- g' = M^T D^-1 m'
-  const C a0 = mp[0] * C(1.0 / 15.0);
-  const C a1 = mp[1] * C(0.1), a2 = mp[2] * C(0.1), a3 = mp[3] * C(0.1);
+  const C a0 = scale_conserved(mp[0], 1.0 / 15.0);
+  const C a1 = scale_conserved(mp[1], 0.1), a2 = scale_conserved(mp[2], 0.1),
+          a3 = scale_conserved(mp[3], 0.1);
   const C a4 = mp[4] * C(1.0 / 18.0), a5 = mp[5] * C(1.0 / 360.0);
   const C a6 = mp[6] * C(0.025), a7 = mp[7] * C(0.025), a8 = mp[8] * C(0.025);
   const C a9 = mp[9] * C(1.0 / 12.0), a10 = mp[10] * C(0.25);

@@ -111,6 +111,23 @@ __device__ __forceinline__ double recip<double>(double x) {
   return 1.0 / x;
 }
 
+// m * (1/D) for a conserved moment (mass or momentum row) with D an integer
+// row norm. In FP32 a product with the rounded 1/D would scale the moment by
+// the same factor at every collision (1 + 7.5e-9 for D = 9, 1 + 3.0e-8 for
+// D = 6), which amplifies the acoustic field linearly in time; the
+// two-term constant hi + lo = 1/D (to 2^-48) makes the result the correctly
+// rounded quotient, whose rounding error varies in sign from value to
+// value. FP64 keeps the plain product (its bias, about 1e-16 per step, stays
+// far below its bars).
+template <typename C>
+__device__ __forceinline__ C scale_conserved(C m, double inv_d) {
+  if (sizeof(C) == 4) {
+    const float hi = (float)inv_d, lo = (float)(inv_d - (double)hi);
+    return fmaC(m, C(hi), m * C(lo));
+  }
+  return m * C(inv_d);
+}
+
 // Deviation of the moment equilibria, dm^eq = m^eq(c_b + dc) - m^eq(c_b).
 template <typename C>
 __device__ __forceinline__ void meq_delta(C dr, C djx, C djy, C rho_b, C ubx,
@@ -228,7 +245,7 @@ __device__ __forceinline__ void collide(C g[9], C chi, const CollideParams<C> &p
       mc[2] = fmaC(chi * inv_m, d2, mc[2]);
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a[k] = mc[k] * C(DINV[k]);
+    for (int k = 0; k < 3; ++k) a[k] = scale_conserved(mc[k], DINV[k]);
   }
   // non-conserved rows, one rate per row (the viscosity ramp raises it per
   // cell). In FP32: a_k = ((1 - s_k)/D_k) dm_k + (s_k/D_k) dm^eq*_k +
