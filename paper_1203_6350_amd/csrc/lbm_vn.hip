@@ -17,11 +17,14 @@
 // exceptional shifts after 10 and 20 stalled sweeps). Eigenvalues are
 // returned sorted by (-|lambda|, arg lambda).
 //
-// Each thread's matrix lives in LDS, laid out [element][thread] (16-byte
-// complex pairs) so that the lanes touch consecutive pairs. The solve is
-// bound by LDS latency with few waves resident (1.3 KB of LDS per
-// wavenumber), so workgroups are 16 threads: more of them fit on a CU
-// (measured: 16 threads 56, 32 threads 54, 64 threads 40 M wavenumbers/s).
+// Each lane holds its wavenumber's matrix in registers (81 complex values,
+// every index fixed at compile time: the loops are fully unrolled), so the
+// solve runs from the register file at the VALU rate. The QR sweeps are
+// wave-wide: every lane runs the same instruction stream over the full
+// 9 x 9 matrix, and a lane's own state (the bottom row of its active window,
+// its shift, its stall counter) enters only through predicates: rotations
+// outside its window are the identity. A wave ends when all its lanes have
+// converged.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -63,21 +66,6 @@ __device__ __forceinline__ cplx sqrtc(cplx z) {
 }
 
 constexpr int N = 9;
-
-// Matrix element (i, j) of this thread; NT threads share the block's LDS,
-// one 16-byte (re, im) pair per element.
-template <int NT>
-struct Mat {
-  double2 *a;
-  int t;
-  __device__ __forceinline__ cplx get(int i, int j) const {
-    const double2 v = a[(i * N + j) * NT + t];
-    return mk(v.x, v.y);
-  }
-  __device__ __forceinline__ void set(int i, int j, cplx v) const {
-    a[(i * N + j) * NT + t] = make_double2(v.re, v.im);
-  }
-};
 
 // The D2Q9 transform of Appendix A.1, row-major; rows (rho, jx, jy, e, eps,
 // qx, qy, pxx, pxy).
@@ -123,51 +111,6 @@ __device__ void build_Am(const VnParamsDev &p, double *Am) {
   }
 }
 
-template <int NT>
-__device__ void hessenberg(const Mat<NT> &H) {
-  for (int k = 0; k < N - 2; ++k) {
-    double xn2 = 0.0;
-    for (int i = k + 1; i < N; ++i) {
-      const cplx v = H.get(i, k);
-      xn2 += v.re * v.re + v.im * v.im;
-    }
-    const double xn = sqrt(xn2);
-    const cplx x0 = H.get(k + 1, k);
-    double tail = 0.0;
-    for (int i = k + 2; i < N; ++i) tail += abs1(H.get(i, k));
-    if (tail == 0.0) continue;  // already reduced in this column
-    const double ax0 = absc(x0);
-    const cplx ph = ax0 > 0.0 ? scal(1.0 / ax0, x0) : mk(1.0, 0.0);
-    const cplx alpha = scal(-xn, ph);  // -e^{i arg x0} ||x||
-    // v = x - alpha e1, normalised
-    cplx v[N];
-    double vn2 = 0.0;
-    for (int i = k + 1; i < N; ++i) {
-      cplx vi = H.get(i, k);
-      if (i == k + 1) vi = sub(vi, alpha);
-      v[i] = vi;
-      vn2 += vi.re * vi.re + vi.im * vi.im;
-    }
-    const double inv = 1.0 / sqrt(vn2);
-    for (int i = k + 1; i < N; ++i) v[i] = scal(inv, v[i]);
-    // left: H <- (I - 2 v v^H) H on rows k+1.., columns k+1..
-    for (int j = k + 1; j < N; ++j) {
-      cplx w = mk(0.0, 0.0);
-      for (int i = k + 1; i < N; ++i) w = add(w, mul(conjc(v[i]), H.get(i, j)));
-      for (int i = k + 1; i < N; ++i) H.set(i, j, sub(H.get(i, j), scal(2.0, mul(v[i], w))));
-    }
-    H.set(k + 1, k, alpha);
-    for (int i = k + 2; i < N; ++i) H.set(i, k, mk(0.0, 0.0));
-    // right: H <- H (I - 2 v v^H) on all rows, columns k+1..
-    for (int i = 0; i < N; ++i) {
-      cplx w = mk(0.0, 0.0);
-      for (int j = k + 1; j < N; ++j) w = add(w, mul(H.get(i, j), v[j]));
-      for (int j = k + 1; j < N; ++j)
-        H.set(i, j, sub(H.get(i, j), scal(2.0, mul(w, conjc(v[j])))));
-    }
-  }
-}
-
 // Eigenvalues of the 2x2 block [a b; c d].
 __device__ void eig2(cplx a, cplx b, cplx c, cplx d, cplx &l1, cplx &l2) {
   const cplx p = scal(0.5, sub(a, d));
@@ -184,89 +127,6 @@ __device__ void eig2(cplx a, cplx b, cplx c, cplx d, cplx &l1, cplx &l2) {
   l2 = sub(d, divc(bc, z1));
 }
 
-template <int NT>
-__device__ bool hqr(const Mat<NT> &H, cplx *ev) {
-  const double eps = 2.220446049250313e-16;
-  int hi = N - 1, iter = 0, total = 0;
-  while (hi >= 0) {
-    if (hi == 0) {
-      ev[0] = H.get(0, 0);
-      break;
-    }
-    int l = hi;
-    for (; l > 0; --l) {
-      const double tst = abs1(H.get(l - 1, l - 1)) + abs1(H.get(l, l));
-      if (abs1(H.get(l, l - 1)) <= eps * tst) {
-        H.set(l, l - 1, mk(0.0, 0.0));
-        break;
-      }
-    }
-    if (l == hi) {
-      ev[hi] = H.get(hi, hi);
-      --hi;
-      iter = 0;
-      continue;
-    }
-    if (l == hi - 1) {
-      eig2(H.get(hi - 1, hi - 1), H.get(hi - 1, hi), H.get(hi, hi - 1), H.get(hi, hi),
-           ev[hi - 1], ev[hi]);
-      hi -= 2;
-      iter = 0;
-      continue;
-    }
-    if (++total > 40 * N) return false;
-    cplx mu;
-    if (iter == 10 || iter == 20) {
-      // exceptional shift
-      mu = add(H.get(hi, hi), mk(0.75 * fabs(H.get(hi, hi - 1).re) + fabs(H.get(hi - 1, hi - 2).re), 0.0));
-    } else {
-      cplx l1, l2;
-      eig2(H.get(hi - 1, hi - 1), H.get(hi - 1, hi), H.get(hi, hi - 1), H.get(hi, hi), l1, l2);
-      const cplx hh = H.get(hi, hi);
-      mu = abs1(sub(l1, hh)) <= abs1(sub(l2, hh)) ? l1 : l2;  // Wilkinson
-    }
-    ++iter;
-    // QR sweep of the active block l..hi: H - mu I = Q R, H <- R Q + mu I
-    for (int k = l; k <= hi; ++k) H.set(k, k, sub(H.get(k, k), mu));
-    double cs[N];
-    cplx sn[N];
-    for (int k = l; k < hi; ++k) {
-      const cplx x = H.get(k, k), y = H.get(k + 1, k);
-      const double ax = absc(x), r = hypot(ax, absc(y));
-      double c;
-      cplx s;
-      if (r == 0.0) {
-        c = 1.0;
-        s = mk(0.0, 0.0);
-      } else if (ax == 0.0) {
-        c = 0.0;
-        s = scal(1.0 / absc(y), conjc(y));
-      } else {
-        c = ax / r;
-        s = scal(1.0 / (ax * r), mul(x, conjc(y)));
-      }
-      cs[k] = c;
-      sn[k] = s;
-      for (int j = k; j <= hi; ++j) {
-        const cplx t1 = H.get(k, j), t2 = H.get(k + 1, j);
-        H.set(k, j, add(scal(c, t1), mul(s, t2)));
-        H.set(k + 1, j, sub(scal(c, t2), mul(conjc(s), t1)));
-      }
-    }
-    for (int k = l; k < hi; ++k) {
-      const double c = cs[k];
-      const cplx s = sn[k];
-      for (int i = l; i <= k + 1; ++i) {
-        const cplx t1 = H.get(i, k), t2 = H.get(i, k + 1);
-        H.set(i, k, add(scal(c, t1), mul(t2, conjc(s))));
-        H.set(i, k + 1, sub(scal(c, t2), mul(t1, s)));
-      }
-    }
-    for (int k = l; k <= hi; ++k) H.set(k, k, add(H.get(k, k), mu));
-  }
-  return true;
-}
-
 __device__ __forceinline__ bool before(cplx a, cplx b) {
   const double ma = absc(a), mb = absc(b);
   if (ma != mb) return ma > mb;
@@ -275,23 +135,229 @@ __device__ __forceinline__ bool before(cplx a, cplx b) {
 
 }  // namespace
 
-template <int NT>
-__global__ __launch_bounds__(NT) void vn_kernel(const VnParamsDev *__restrict__ params,
+// 1/sqrt(x) for x > 0 to about one ulp: the hardware estimate refined by
+// two Newton steps (each doubles the correct bits).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * __builtin_fma(-hx * y, y, 1.5);
+  y = y * __builtin_fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// One lane's matrix: H = R + i I, row-major, static indices only.
+struct RegMat {
+  double r[N][N], m[N][N];
+  __device__ __forceinline__ cplx at(int i, int j) const { return mk(r[i][j], m[i][j]); }
+  __device__ __forceinline__ void put(int i, int j, cplx v) {
+    r[i][j] = v.re;
+    m[i][j] = v.im;
+  }
+};
+
+// Element (i, j) of the tridiagonal band (|i - j| <= 1) at the lane's own
+// (run-time) indices, read by selecting over the static positions.
+__device__ __forceinline__ cplx pick(const RegMat &H, int i, int j) {
+  cplx v = mk(0.0, 0.0);
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+      if (b >= a - 1 && b <= a + 1) {  // the sub-, main and superdiagonal are all we read
+        const bool hit = a == i && b == j;
+        v.re = hit ? H.r[a][b] : v.re;
+        v.im = hit ? H.m[a][b] : v.im;
+      }
+  return v;
+}
+
+// Householder reduction to upper Hessenberg form, H <- Q^H H Q.
+__device__ __forceinline__ void hessenberg_reg(RegMat &H) {
+#pragma unroll
+  for (int k = 0; k < N - 2; ++k) {
+    double xn2 = 0.0;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) xn2 += H.r[i][k] * H.r[i][k] + H.m[i][k] * H.m[i][k];
+    const double xn = sqrt(xn2);
+    const cplx x0 = H.at(k + 1, k);
+    const double ax0 = absc(x0);
+    const cplx ph = ax0 > 0.0 ? scal(1.0 / ax0, x0) : mk(1.0, 0.0);
+    const cplx alpha = scal(-xn, ph);  // -e^{i arg x0} ||x||
+    // v = x - alpha e1, normalised (v = 0, the identity, for a zero column)
+    cplx v[N];
+    double vn2 = 0.0;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      v[i] = i == k + 1 ? sub(x0, alpha) : H.at(i, k);
+      vn2 += v[i].re * v[i].re + v[i].im * v[i].im;
+    }
+    const double inv = vn2 > 0.0 ? rsqrt_f64(vn2) : 0.0;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) v[i] = scal(inv, v[i]);
+    // left: rows k+1.., columns k+1..
+#pragma unroll
+    for (int j = k + 1; j < N; ++j) {
+      cplx w = mk(0.0, 0.0);
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) w = add(w, mul(conjc(v[i]), H.at(i, j)));
+      w = scal(2.0, w);
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) H.put(i, j, sub(H.at(i, j), mul(v[i], w)));
+    }
+    // column k below the subdiagonal: the reflection maps x to alpha e1
+    // (with v = 0 the column was zero below x0 already); the entries below
+    // the subdiagonal become compile-time zeros, which frees their registers
+    // for the QR sweeps (they never read them)
+    H.put(k + 1, k, vn2 > 0.0 ? alpha : x0);
+#pragma unroll
+    for (int i = k + 2; i < N; ++i) H.put(i, k, mk(0.0, 0.0));
+    // right: all rows, columns k+1..
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      cplx w = mk(0.0, 0.0);
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) w = add(w, mul(H.at(i, j), v[j]));
+      w = scal(2.0, w);
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) H.put(i, j, sub(H.at(i, j), mul(w, conjc(v[j]))));
+    }
+  }
+}
+
+// Rotation [c s; -conj(s) conj(c)] with c = conj(x)/r, s = conj(y)/r,
+// r = sqrt(|x|^2 + |y|^2), which maps (x, y) to (r, 0); the identity when
+// inactive or when x = y = 0.
+__device__ __forceinline__ void givens(cplx x, cplx y, bool act, cplx &c, cplx &s) {
+  const double n2 = x.re * x.re + x.im * x.im + y.re * y.re + y.im * y.im;
+  const bool on = act && n2 > 0.0;
+  const double ir = on ? rsqrt_f64(n2) : 0.0;
+  c = on ? mk(x.re * ir, -x.im * ir) : mk(1.0, 0.0);
+  s = on ? mk(y.re * ir, -y.im * ir) : mk(0.0, 0.0);
+}
+
+// H <- H G^H on columns q, q + 1 for rows 0..rmax, G = [c s; -conj(s) conj(c)].
+__device__ __forceinline__ void right_rot(RegMat &H, int q, int rmax, cplx c, cplx s) {
+#pragma unroll
+  for (int i = 0; i <= rmax; ++i) {
+    const cplx t1 = H.at(i, q), t2 = H.at(i, q + 1);
+    H.put(i, q, add(mul(t1, conjc(c)), mul(t2, conjc(s))));
+    H.put(i, q + 1, sub(mul(t2, c), mul(t1, s)));
+  }
+}
+
+constexpr int VN_MAX_SWEEPS = 40 * N;
+
+// Eigenvalues of the upper Hessenberg H by single-shift QR sweeps on the
+// lane's active window 0..hi (Wilkinson shift from its trailing 2 x 2,
+// exceptional shifts after 10 and 20 stalled sweeps; the bottom eigenvalue
+// deflates when its subdiagonal is negligible). Returns false if the lane
+// did not converge within VN_MAX_SWEEPS sweeps.
+__device__ __forceinline__ bool qr_reg(RegMat &H, double2 *ev, int stride) {
+  const double eps = 2.220446049250313e-16;
+  int hi = N - 1, it = 0;
+  bool done = false;
+  for (int sweep = 0; sweep < VN_MAX_SWEEPS; ++sweep) {
+    // deflate converged eigenvalues at the bottom (two checks per sweep)
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      if (!done) {
+        if (hi <= 0) {
+          ev[0] = make_double2(H.r[0][0], H.m[0][0]);
+          done = true;
+        } else {
+          const cplx d = pick(H, hi, hi - 1);
+          const cplx a = pick(H, hi - 1, hi - 1), b = pick(H, hi, hi);
+          if (abs1(d) <= eps * (abs1(a) + abs1(b))) {
+            ev[hi * stride] = make_double2(b.re, b.im);
+            --hi;
+            it = 0;
+          } else if (hi == 1) {
+            cplx l0, l1;
+            eig2(a, pick(H, 0, 1), d, b, l0, l1);
+            ev[0] = make_double2(l0.re, l0.im);
+            ev[stride] = make_double2(l1.re, l1.im);
+            done = true;
+          }
+        }
+      }
+    }
+    if (__all(done)) break;
+    // shift of the active window
+    cplx mu = mk(0.0, 0.0);
+    if (!done) {
+      const cplx a = pick(H, hi - 1, hi - 1), b = pick(H, hi - 1, hi);
+      const cplx c = pick(H, hi, hi - 1), d = pick(H, hi, hi);
+      if (it == 10 || it == 20) {
+        const double e2 = hi >= 2 ? fabs(pick(H, hi - 1, hi - 2).re) : 0.0;
+        mu = add(d, mk(0.75 * fabs(c.re) + e2, 0.0));
+      } else {
+        cplx l1, l2;
+        eig2(a, b, c, d, l1, l2);
+        mu = abs1(sub(l1, d)) <= abs1(sub(l2, d)) ? l1 : l2;
+      }
+      ++it;
+    }
+    // H - mu I on the window
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const bool in = !done && i <= hi;
+      H.r[i][i] -= in ? mu.re : 0.0;
+      H.m[i][i] -= in ? mu.im : 0.0;
+    }
+    // R = G_{hi-1} ... G_0 (H - mu I), then R G_0^H ... G_{hi-1}^H, with
+    // each right rotation applied once the next left one is: the left
+    // rotation k reads H(k, k) before the right rotation k - 1 changes it.
+    // Rotations that no lane of the wave needs (k >= hi in every lane) are
+    // skipped as a whole; a pending right rotation is applied first.
+    cplx cp = mk(1.0, 0.0), sp = mk(0.0, 0.0);
+    bool pend = false;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+      if (__any(!done && k < hi)) {
+        cplx c, s;
+        givens(H.at(k, k), H.at(k + 1, k), !done && k < hi, c, s);
+#pragma unroll
+        for (int j = k; j < N; ++j) {
+          const cplx t1 = H.at(k, j), t2 = H.at(k + 1, j);
+          H.put(k, j, add(mul(c, t1), mul(s, t2)));
+          H.put(k + 1, j, sub(mul(conjc(c), t2), mul(conjc(s), t1)));
+        }
+        if (k > 0) right_rot(H, k - 1, k, cp, sp);
+        cp = c;
+        sp = s;
+        pend = true;
+      } else if (pend) {
+        right_rot(H, k - 1, k, cp, sp);
+        pend = false;
+      }
+    }
+    if (pend) right_rot(H, N - 2, N - 1, cp, sp);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const bool in = !done && i <= hi;
+      H.r[i][i] += in ? mu.re : 0.0;
+      H.m[i][i] += in ? mu.im : 0.0;
+    }
+  }
+  return done;
+}
+
+// One wavenumber per lane, 64 lanes per workgroup (one wave); blockIdx.y
+// is the parameter set.
+__global__ __launch_bounds__(64) void vn_kernel(const VnParamsDev *__restrict__ params,
                                                 int64_t nk,
                                                 const double *__restrict__ kx,
                                                 const double *__restrict__ ky,
                                                 double *__restrict__ eig,
                                                 double *__restrict__ G) {
-  extern __shared__ double smem[];
-  double *Are = smem;                  // 81: A = M^-1 A_m M
-  double *Am = smem + 81;              // 81
-  double2 *Hm = (double2 *)(smem + 162);  // 81 * NT (re, im) pairs
+  __shared__ double Are[81];  // A = M^-1 A_m M
+  __shared__ double Am[81];
+  __shared__ double2 evs[N * 64];  // eigenvalues as they deflate, [index][lane]
   const int pset = blockIdx.y;
-  const VnParamsDev p = params[pset];
   const int t = threadIdx.x;
-  if (t == 0) build_Am(p, Am);
+  if (t == 0) build_Am(params[pset], Am);
   __syncthreads();
-  for (int e = t; e < 81; e += NT) {
+  for (int e = t; e < 81; e += 64) {
     const int i = e / 9, j = e % 9;
     double acc = 0.0;
     for (int k = 0; k < 9; ++k) {
@@ -302,32 +368,41 @@ __global__ __launch_bounds__(NT) void vn_kernel(const VnParamsDev *__restrict__ 
     Are[e] = acc;
   }
   __syncthreads();
-  const int64_t kidx = (int64_t)blockIdx.x * NT + t;
-  if (kidx >= nk) return;
-  const double k1 = kx[kidx], k2 = ky[kidx];
-  Mat<NT> H{Hm, t};
-  for (int i = 0; i < 9; ++i) {
+  const int64_t kidx = (int64_t)blockIdx.x * 64 + t;
+  // lanes past the end solve a copy of the last wavenumber and store nothing,
+  // so that every lane of the wave runs the same sweeps
+  const int64_t kk = kidx < nk ? kidx : nk - 1;
+  const double k1 = kx[kk], k2 = ky[kk];
+  RegMat H;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
     const double ph = -(k1 * cx_of(i) + k2 * cy_of(i));
     double sp, cp;
     sincos(ph, &sp, &cp);
-    for (int j = 0; j < 9; ++j) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
       const double a = Are[i * 9 + j];
-      H.set(i, j, mk(cp * a, sp * a));
+      H.r[i][j] = cp * a;
+      H.m[i][j] = sp * a;
     }
   }
   const int64_t out = (int64_t)pset * nk + kidx;
-  if (G) {
+  if (G && kidx < nk) {
+#pragma unroll
     for (int e = 0; e < 81; ++e) {
-      const cplx v = H.get(e / 9, e % 9);
-      G[(out * 81 + e) * 2] = v.re;
-      G[(out * 81 + e) * 2 + 1] = v.im;
+      G[(out * 81 + e) * 2] = H.r[e / 9][e % 9];
+      G[(out * 81 + e) * 2 + 1] = H.m[e / 9][e % 9];
     }
   }
-  hessenberg(H);
+  hessenberg_reg(H);
+  const bool ok = qr_reg(H, evs + t, 64);
+  if (kidx >= nk) return;
   cplx ev[N];
-  const bool ok = hqr(H, ev);
-  if (!ok)
-    for (int i = 0; i < N; ++i) ev[i] = mk(__builtin_nan(""), __builtin_nan(""));
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double2 v = evs[i * 64 + t];
+    ev[i] = ok ? mk(v.x, v.y) : mk(__builtin_nan(""), __builtin_nan(""));
+  }
   // insertion sort by (-|lambda|, arg lambda)
   for (int i = 1; i < N; ++i) {
     const cplx v = ev[i];
@@ -344,22 +419,15 @@ __global__ __launch_bounds__(NT) void vn_kernel(const VnParamsDev *__restrict__ 
   }
 }
 
-template <int NT>
-static hipError_t launch_vn_t(const VnParamsDev *params_dev, int nparams, int64_t nk,
-                              const double *kx, const double *ky, double *eig,
-                              double *G, hipStream_t stream) {
-  const size_t shmem = sizeof(double) * (162 + 2 * 81 * NT);
-  const int64_t bx = (nk + NT - 1) / NT;
-  if (bx > 0x7fffffff) return hipErrorInvalidValue;
-  vn_kernel<NT><<<dim3((unsigned)bx, (unsigned)nparams), dim3(NT), shmem, stream>>>(
-      params_dev, nk, kx, ky, eig, G);
-  return hipGetLastError();
-}
-
 hipError_t launch_vn(const VnParamsDev *params_dev, int nparams, int64_t nk,
                      const double *kx, const double *ky, double *eig, double *G,
                      hipStream_t stream) {
-  return launch_vn_t<16>(params_dev, nparams, nk, kx, ky, eig, G, stream);
+  if (nk < 1) return hipSuccess;
+  const int64_t bx = (nk + 63) / 64;
+  if (bx > 0x7fffffff) return hipErrorInvalidValue;
+  vn_kernel<<<dim3((unsigned)bx, (unsigned)nparams), dim3(64), 0, stream>>>(
+      params_dev, nk, kx, ky, eig, G);
+  return hipGetLastError();
 }
 
 }  // namespace lbm

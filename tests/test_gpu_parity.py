@@ -352,7 +352,44 @@ VN_SETS = wl.vn_param_sets(24)
 
 
 @pytest.mark.parametrize("idx", range(len(VN_SETS)))
+def eig_tolerances(Gk):
+    """LAPACK eigenvalues of one G(k) and a tolerance for each: 1e-12 ||G||
+    for a well-conditioned eigenvalue, widened by its condition number
+    kappa = ||x|| ||y|| / |y^H x| (first-order perturbation: two backward
+    stable solvers differ by a few eps ||G|| kappa), and for a defective or
+    nearly defective cluster (kappa eps > 1e-8, the six-fold 1 - s near
+    k = 0) the Hoelder bound of a cluster, 1e-5 ||G||."""
+    import scipy.linalg
+    w, vl, vr = scipy.linalg.eig(Gk, left=True, right=True)
+    kappa = np.array([np.linalg.norm(vl[:, i]) * np.linalg.norm(vr[:, i])
+                      / max(abs(np.vdot(vl[:, i], vr[:, i])), 1e-300) for i in range(9)])
+    nrm = np.linalg.norm(Gk, 2)
+    eps = np.finfo(float).eps
+    tol = np.where(kappa * eps > 1e-8, 1e-5, np.maximum(1e-12, 64 * eps * kappa)) * nrm
+    return w, tol, kappa
+
+
+def check_spectrum(lam, Gk):
+    """Greedy matching of the GPU eigenvalues to LAPACK's, each within its
+    own tolerance; returns the largest error in units of ||G||."""
+    ref, tol, _ = eig_tolerances(Gk)
+    free = list(range(9))
+    worst = 0.0
+    for x in sorted(lam, key=lambda z: -abs(z)):
+        j = min(free, key=lambda q: abs(x - ref[q]))
+        assert abs(x - ref[j]) <= tol[j], (x, ref[j], tol[j])
+        worst = max(worst, abs(x - ref[j]) / np.linalg.norm(Gk, 2))
+        free.remove(j)
+    return worst
+
+
+@pytest.mark.parametrize("idx", range(len(VN_SETS)))
 def test_vn_matches_lapack(idx):
+    """G(k) elementwise within 1e-13 of the oracle's complex-step matrix;
+    eigenvalues within 1e-12 ||G|| of LAPACK's wherever they are well
+    conditioned (condition-scaled elsewhere, see eig_tolerances); sorted by
+    (-|lambda|, arg lambda); prod lambda = det A within 1e-13 for every k
+    (det E(k) = 1 because the velocities sum to zero)."""
     p = VN_SETS[idx]
     say("case: VN set", idx, p["variant"], p["chi"])
     g = np.random.default_rng(idx)
@@ -362,25 +399,22 @@ def test_vn_matches_lapack(idx):
     A = vn.linearized_collision(p["s"], p["chi"], p["qref"], p["n"], p["m"], p["variant"])
     Gr = vn.amplification(A, kx, ky)
     np.testing.assert_allclose(G, Gr, rtol=0, atol=1e-13)
-    ref = np.linalg.eigvals(Gr)
+    worst = 0.0
     for i in range(len(kx)):
-        # clustered spectra (six-fold 1 - s near k = 0) are ill-conditioned:
-        # eigenvalue error ~ eps^(1/m); compare against a cluster-aware bound
-        tol = 1e-10 if abs(kx[i]) + abs(ky[i]) > 0.05 else 1e-5
-        assert match_eigs(lam[i], ref[i]) <= tol, (i, kx[i], ky[i])
-        # sorted by (-|lambda|, arg)
+        worst = max(worst, check_spectrum(lam[i], Gr[i]))
         mags = np.abs(lam[i])
         assert np.all(np.diff(mags) <= 1e-12)
-    # det invariant: prod lambda = det A for every k
+    say("  largest |dlambda| / ||G||: %.2e" % worst)
     detA = np.linalg.det(A)
-    np.testing.assert_allclose(np.prod(lam, axis=1), detA, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(np.prod(lam, axis=1), detA, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("nk", [0, 1, 15, 16, 17])
+@pytest.mark.parametrize("nk", [0, 1, 15, 16, 17, 63, 64, 65, 130])
 def test_vn_empty_single_and_ragged_sweeps(nk):
-    """No wavenumbers, one, and one lane short of, at and past a workgroup's
-    16: each spectrum equals LAPACK's, and a wavenumber's result does not
-    depend on the others in its sweep."""
+    """No wavenumbers, one, and sweeps around a 16-lane boundary: each
+    spectrum equals LAPACK's, and a wavenumber's result does not depend on
+    the others in its sweep (lanes past the end of a wave solve a copy and
+    store nothing)."""
     p = VN_SETS[5]
     g = np.random.default_rng(100 + nk)
     kx, ky = g.uniform(-np.pi, np.pi, nk), g.uniform(-np.pi, np.pi, nk)
@@ -391,9 +425,8 @@ def test_vn_empty_single_and_ragged_sweeps(nk):
     A = vn.linearized_collision(p["s"], p["chi"], p["qref"], p["n"], p["m"], p["variant"])
     Gr = vn.amplification(A, kx, ky)
     np.testing.assert_allclose(G, Gr, rtol=0, atol=1e-13)
-    ref = np.linalg.eigvals(Gr)
     for i in range(nk):
-        assert match_eigs(lam[i], ref[i]) <= 1e-10, (i, kx[i], ky[i])
+        check_spectrum(lam[i], Gr[i])
     alone = lbm.vn_amplification(p, kx[-1:], ky[-1:])
     assert np.array_equal(alone[0], lam[-1])
 
