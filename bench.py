@@ -192,8 +192,12 @@ def make_domain(lbm, spec, stream):
 
 
 def batched_leg(lbm, wl, torch, steps=1000, vn_sets=64, vn_nk=256):
-    """256 uneven domains: one persistent launch per step (graph-captured)
-    against plain per-domain launches; plus the Von Neumann sweep."""
+    """256 uneven domains: the batch (persistent launches captured in HIP
+    graphs) against plain per-domain launches, three ways: one eager
+    one-step launch per domain per step; each domain in its own autotuned
+    shape, one after another; the same spread over eight streams. Finite
+    members are compared bit for bit with the batch. Plus the Von Neumann
+    sweep."""
     specs = wl.batch_c4()
     cells = sum(sp.nx * sp.ny for sp in specs)
     s = torch.cuda.current_stream()
@@ -207,6 +211,27 @@ def batched_leg(lbm, wl, torch, steps=1000, vn_sets=64, vn_nk=256):
         lat.step(steps)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    # plain, each domain in its own autotuned launch shape (K steps per
+    # launch where that is fastest), one after another on one stream, and
+    # spread round-robin over eight streams
+    tuned_t = {}
+    for nstreams in (1, 8):
+        streams = [s] if nstreams == 1 else [torch.cuda.Stream() for _ in range(nstreams)]
+        tuned = [make_domain(lbm, sp, streams[i % nstreams]) for i, sp in enumerate(specs)]
+        for lat in tuned:
+            lat.autotune(reps=3)
+            lat.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lat in tuned:
+            lat.step(steps)
+        torch.cuda.synchronize()
+        tuned_t[nstreams] = time.perf_counter() - t0
+        if nstreams == 8:
+            tuned_8 = tuned
+        else:
+            for lat in tuned:
+                lat.close()
     # batched: the same domains, same number of steps
     lats = [make_domain(lbm, sp, s) for sp in specs]
     b = lbm.Batch(lats)
@@ -225,13 +250,21 @@ def batched_leg(lbm, wl, torch, steps=1000, vn_sets=64, vn_nk=256):
             unstable += 1
             continue
         same = same and bool((p_.save_state() == q_.save_state()).all())
+    for p_, q_ in zip(tuned_8, lats):
+        if p_.diagnostics()[6] == 0:
+            same = same and bool((p_.save_state() == q_.save_state()).all())
     b.close()
-    for lat in plain + lats:
+    for lat in plain + lats + tuned_8:
         lat.close()
     out = {"domains": len(specs), "cells": cells, "steps": steps,
            "batched_mlups": cells * steps / t_batch / 1e6,
            "plain_mlups": cells * steps / t_plain / 1e6,
-           "speedup": t_plain / t_batch, "bitwise_equal_finite_members": same,
+           "speedup": t_plain / t_batch,
+           "plain_tuned_mlups": cells * steps / tuned_t[1] / 1e6,
+           "speedup_vs_tuned": tuned_t[1] / t_batch,
+           "plain_tuned_8streams_mlups": cells * steps / tuned_t[8] / 1e6,
+           "speedup_vs_tuned_8streams": tuned_t[8] / t_batch,
+           "bitwise_equal_finite_members": same,
            "unstable_members": unstable}
     out.update(vn_sweep_leg(lbm, wl, torch, vn_sets, vn_nk))
     return out

@@ -140,6 +140,16 @@ int lbm_set_sponge_separable(lbm_handle *h, const double *chi_x,
                              const double *chi_y, int32_t combine,
                              const lbm_qref *q);
 
+/* As lbm_set_sponge_separable with the profiles in device memory (FP64
+ * chi_x[nx], chi_y[ny], either may be NULL for zeros), for callers that set
+ * up lattices on a busy stream (a server admitting requests): everything is
+ * enqueued on the handle's stream and the call does not wait. The profiles
+ * are not validated (they must be finite and >= 0, and in [0, 1] for the
+ * viscosity ramp) and must stay valid until the enqueued work completes. */
+int lbm_set_sponge_separable_dev(lbm_handle *h, const double *chi_x,
+                                 const double *chi_y, int32_t combine,
+                                 const lbm_qref *q);
+
 /* Enqueue n >= 0 time steps (collision with the damping term of the
  * handle's variant, then streaming) on the handle's stream and return
  * without waiting. */
@@ -326,7 +336,8 @@ const char *lbm_last_error(void);
  * size, relaxation rates, damping variant, sponge and reference state) with
  * persistent launches captured in HIP graphs: by default each launch
  * advances every member by K steps (the strip kernel over a table of work
- * items; K = 4 for FP32 storage, 3 for FP64 and FP16) and a member's
+ * items, which its workgroups take one by one, tallest first; K = 4 for
+ * FP32 storage, 3 for FP64 and FP16) and a member's
  * remainder of fewer than K steps in a tick runs as one-step launches over
  * a table of 256-cell tiles. A batch whose work items do not fill the
  * device once (few or small members) runs its ticks as one-step tile
@@ -353,9 +364,15 @@ int lbm_batch_step(lbm_batch *b, int64_t n);
  * that finish early keep their state for the rest of the tick. */
 int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps);
 
-/* Replace the member list (same rules as lbm_batch_create). The tile table
- * is rewritten in place when it fits, so graphs captured earlier stay valid.
- * Synchronises the batch stream. */
+/* Replace the member list (same rules as lbm_batch_create) for the ticks
+ * enqueued after this call. Stream-ordered: the tile and item tables are
+ * copied on the batch stream behind the work already enqueued there and
+ * rewritten in place when they fit, so graphs captured earlier stay valid
+ * and the call does not wait for the device; it waits only when a table
+ * outgrows its buffer, and for a member whose own stream is not the batch
+ * stream (so that work enqueued for it there is done). A handle dropped
+ * from the list may be destroyed once the ticks that still advance it have
+ * completed. */
 int lbm_batch_set_members(lbm_batch *b, lbm_handle *const *members,
                           int32_t count);
 
@@ -367,9 +384,11 @@ int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu);
  * launches over 256-cell tiles only (block and rows ignored); kernel 2, 3
  * or 4 = that many steps per launch of the strip kernel, `block` threads per
  * workgroup (64, 128, 256 or 512: adjacent strips of one member), `rows`
- * rows per work item (1..4096, or 0 for a height that gives about three
- * items per resident workgroup). Default: K as above, block 64, rows 32. Rebuilds the work-item table; synchronises the
- * batch stream. Results are bit-identical for every shape. */
+ * rows per work item (1..4096, or 0 for an automatic height: the member
+ * rows over the resident workgroups, so that a launch has an item for each,
+ * clamped to 8..64 rows). Default: K as above, block 128, rows 0. Rebuilds
+ * the work-item table; synchronises the batch stream. Results are
+ * bit-identical for every shape. */
 int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t);
 int lbm_batch_get_tuning(lbm_batch *b, lbm_tuning *t);
 

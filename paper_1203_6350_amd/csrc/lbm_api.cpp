@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <string>
@@ -44,15 +45,26 @@ int hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 int check_device(int *dev_out) {
+  // the architecture of a device is looked up once (hipGetDeviceProperties
+  // takes milliseconds, and lattices are created per request when serving)
+  constexpr int MAXDEV = 64;
+  static std::atomic<int> arch_ok[MAXDEV] = {};  // 0 unknown, 1 gfx950, -1 other
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(LBM_EDEVICE, std::string("liblbm is built for gfx950, device is ") +
-                                 prop.gcnArchName);
+  const int known = dev >= 0 && dev < MAXDEV ? arch_ok[dev].load(std::memory_order_relaxed) : 0;
+  if (known == 0) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev >= 0 && dev < MAXDEV) arch_ok[dev].store(ok ? 1 : -1, std::memory_order_relaxed);
+    if (!ok)
+      return fail(LBM_EDEVICE, std::string("liblbm is built for gfx950, device is ") +
+                                   prop.gcnArchName);
+  } else if (known < 0) {
+    return fail(LBM_EDEVICE, "liblbm is built for gfx950; the current device is not one");
+  }
   if (dev_out) *dev_out = dev;
   return LBM_OK;
 }
@@ -305,8 +317,9 @@ int init_state(lbm_handle *h, const double *rho, const double *ux,
   hipError_t e = lbm::launch_init(h->cfg, d, d ? d + N : nullptr, d ? d + 2 * N : nullptr,
                                   h->lat[0], h->stream);
   if (d) (void)hipFreeAsync(d, h->stream);
-  // the host arrays (and the zero vector) must outlive the copies
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  // the host arrays (and the zero vector) must outlive the copies; without
+  // them nothing waits (a server creates lattices on a busy stream)
+  if (e == hipSuccess && d) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(e, "init kernel");
   h->cur = 0;
   h->steps = 0;
@@ -458,6 +471,33 @@ int lbm_set_sponge_separable(lbm_handle *h, const double *chi_x,
     rc = upload_compute(h, ax.data(), ax.size(), &h->chi_x);
     if (!rc) rc = upload_compute(h, ay.data(), ay.size(), &h->chi_y);
     if (rc) return rc;
+    h->cfg.chi_mode = combine == LBM_COMBINE_MAX ? lbm::CHI_SEP_MAX : lbm::CHI_SEP_SUM;
+  } else {
+    h->cfg.chi_mode = lbm::CHI_ZERO;
+  }
+  if (q) h->q = *q;
+  fill_cfg(h);
+  return LBM_OK;
+}
+
+int lbm_set_sponge_separable_dev(lbm_handle *h, const double *chi_x, const double *chi_y,
+                                 int32_t combine, const lbm_qref *q) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (combine != LBM_COMBINE_MAX && combine != LBM_COMBINE_SUM)
+    return fail(LBM_EINVAL, "unknown combine mode");
+  int rc = check_qref(q);
+  if (rc) return rc;
+  // stream-ordered throughout: the old arrays are freed behind the work
+  // that reads them, the new ones converted behind that
+  free_sponge(h);
+  if (chi_x || chi_y) {
+    const size_t eb = h->user.storage == LBM_STORAGE_F64 ? 8 : 4;
+    HIP_TRY(hipMallocAsync(&h->chi_x, eb * h->user.nx, h->stream), "hipMallocAsync(sponge)");
+    HIP_TRY(hipMallocAsync(&h->chi_y, eb * h->user.ny, h->stream), "hipMallocAsync(sponge)");
+    HIP_TRY(lbm::launch_convert_profile(h->user.storage, chi_x, h->chi_x, h->user.nx, h->stream),
+            "sponge conversion");
+    HIP_TRY(lbm::launch_convert_profile(h->user.storage, chi_y, h->chi_y, h->user.ny, h->stream),
+            "sponge conversion");
     h->cfg.chi_mode = combine == LBM_COMBINE_MAX ? lbm::CHI_SEP_MAX : lbm::CHI_SEP_SUM;
   } else {
     h->cfg.chi_mode = lbm::CHI_ZERO;
@@ -940,8 +980,8 @@ struct lbm_batch {
   int blocks_per_cu = 8;
   // K-step strip launches (multi_k = 0: one-step tile launches only)
   int multi_k = 0;
-  int multi_nw = 1;    // waves per workgroup
-  int multi_rows = 32; // rows per work item, 0: about three items per resident workgroup
+  int multi_nw = 2;    // waves per workgroup
+  int multi_rows = 0;  // rows per work item, 0: automatic (8..64, an item per resident workgroup)
   int multi_grid = 0;  // persistent workgroups of the strip kernel
   int min_items = -1;  // strip launches need this many items (-1: multi_grid)
   int4 *d_items = nullptr;
@@ -955,6 +995,12 @@ struct lbm_batch {
   lbm::CheckDesc *d_chk = nullptr;                 // [dom_cap]
   lbm::CheckDesc *h_chk[2] = {nullptr, nullptr};   // pinned staging, alternating
   hipEvent_t chk_copied[2] = {nullptr, nullptr};
+  // pinned staging of the tile and item tables (member changes are
+  // stream-ordered: no wait for the device unless a table outgrows its buffer)
+  char *h_tab[2] = {nullptr, nullptr};
+  size_t tab_cap[2] = {0, 0};
+  hipEvent_t tab_copied[2] = {nullptr, nullptr};
+  int tab_slot = 0;
   int chk_slot = 0;
   bool any_detector = false;  // some check ran since the member list was set
   // graphs keyed by (K or 0, K-step launches or ticks, remainder launches,
@@ -1021,6 +1067,9 @@ int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, hipGraphExec_t *ou
   }
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   hipError_t e = hipSuccess;
+  // zero the item tickets of the tick's strip launches (a kernel node: the
+  // graph is replayed every tick)
+  if (nmulti > 0) e = lbm::launch_fill_i32(b->d_nitems + 1, nmulti, 0, b->stream);
   for (int j = 0; j < nmulti && e == hipSuccess; ++j)
     e = lbm::launch_batch_multi(b->storage, K, b->multi_nw, b->multi_def, b->d_doms,
                                 b->d_items, b->d_nitems, b->multi_grid, j, b->stream);
@@ -1061,6 +1110,8 @@ void lbm_batch_destroy(lbm_batch *b) {
     if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
     if (b->h_chk[k]) (void)hipHostFree(b->h_chk[k]);
     if (b->chk_copied[k]) (void)hipEventDestroy(b->chk_copied[k]);
+    if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+    if (b->tab_copied[k]) (void)hipEventDestroy(b->tab_copied[k]);
   }
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -1090,11 +1141,55 @@ int validate_members(lbm_handle *const *members, int32_t count) {
   return LBM_OK;
 }
 
-// Rebuild the strip work-item table for the batch's members and K-step
-// shape; reuses the device buffer (and so the captured graphs) when it fits.
-// The stream must be idle.
-int build_items(lbm_batch *b) {
-  if (!b->multi_k) return LBM_OK;
+// Copy the tile table (optional) and the item table to the device through
+// the next pinned staging slot, in stream order on the batch stream: the
+// copies land after every launch enqueued before them.
+int upload_tables(lbm_batch *b, const std::vector<int2> *tiles, const std::vector<int4> *items) {
+  const int sl = b->tab_slot;
+  b->tab_slot ^= 1;
+  HIP_TRY(hipEventSynchronize(b->tab_copied[sl]), "hipEventSynchronize");  // slot free again
+  const size_t tb = tiles ? sizeof(int2) * tiles->size() : 0;
+  const size_t ib = items ? sizeof(int4) * items->size() : 0;
+  const size_t need = tb + ib + 16;
+  if (need > b->tab_cap[sl]) {
+    if (b->h_tab[sl]) (void)hipHostFree(b->h_tab[sl]);
+    b->h_tab[sl] = nullptr;
+    b->tab_cap[sl] = 0;
+    const size_t cap = std::max<size_t>(need, (size_t)(1.5 * need));
+    HIP_TRY(hipHostMalloc((void **)&b->h_tab[sl], cap, hipHostMallocDefault), "batch table staging");
+    b->tab_cap[sl] = cap;
+  }
+  char *h = b->h_tab[sl];
+  size_t off = 0;
+  if (tiles) {
+    std::memcpy(h, tiles->data(), tb);
+    std::memcpy(h + tb, &b->ntiles, sizeof(int));
+    HIP_TRY(hipMemcpyAsync(b->d_tiles, h, tb, hipMemcpyHostToDevice, b->stream), "copy(tiles)");
+    HIP_TRY(hipMemcpyAsync(b->d_ntiles, h + tb, sizeof(int), hipMemcpyHostToDevice, b->stream),
+            "copy(ntiles)");
+    off = tb + 8;
+  }
+  if (items) {
+    std::memcpy(h + off, items->data(), ib);
+    std::memcpy(h + off + ib, &b->nitems, sizeof(int));
+    if (ib)
+      HIP_TRY(hipMemcpyAsync(b->d_items, h + off, ib, hipMemcpyHostToDevice, b->stream), "copy(items)");
+    HIP_TRY(hipMemcpyAsync(b->d_nitems, h + off + ib, sizeof(int), hipMemcpyHostToDevice, b->stream),
+            "copy(nitems)");
+  }
+  HIP_TRY(hipEventRecord(b->tab_copied[sl], b->stream), "hipEventRecord");
+  return LBM_OK;
+}
+
+// The strip work-item table for the batch's members and K-step shape
+// (empty without K-step launches); reallocates the device table, after
+// waiting for the batch stream, only when it outgrows its buffer.
+int make_items(lbm_batch *b, std::vector<int4> &items) {
+  items.clear();
+  if (!b->multi_k) {
+    b->nitems = 0;
+    return LBM_OK;
+  }
   const int W = 64 - 2 * b->multi_k;
   const int nw = b->multi_nw;
   b->multi_def = true;
@@ -1107,12 +1202,12 @@ int build_items(lbm_batch *b) {
     const int64_t ngroups = ((h->user.nx + W - 1) / W + nw - 1) / nw;
     group_rows += ngroups * h->user.ny;
   }
-  // automatic height: about three items per resident workgroup, so members
-  // of unequal size still balance over the persistent grid
-  const int64_t slots = 3 * (int64_t)b->multi_grid;
-  const int64_t rows = b->multi_rows > 0 ? b->multi_rows
-                                         : std::max<int64_t>(1, (group_rows + slots - 1) / slots);
-  std::vector<int4> items;
+  // automatic height: at least one item per resident workgroup (so that
+  // the K-step launches fill the device even for a few small members),
+  // at most 64 rows (the best height on large batches), at least 8 rows
+  const int64_t rows =
+      b->multi_rows > 0 ? b->multi_rows
+                        : std::min<int64_t>(64, std::max<int64_t>(8, group_rows / b->multi_grid));
   for (size_t i = 0; i < b->members.size(); ++i) {
     const lbm_handle *h = b->members[i];
     const int nstrips = (h->user.nx + W - 1) / W;
@@ -1120,8 +1215,14 @@ int build_items(lbm_batch *b) {
       for (int s0 = 0; s0 < nstrips; s0 += nw)
         items.push_back(make_int4((int)i, s0, (int)y0, (int)std::min<int64_t>(rows, h->user.ny - y0)));
   }
+  // tallest items first: the workgroups take them in this order, so the
+  // short ones (members' last chunks) fill the end of a launch
+  std::stable_sort(items.begin(), items.end(),
+                   [](const int4 &a, const int4 &c) { return a.w > c.w; });
   if (items.size() > (size_t)0x7fffffff) return fail(LBM_EINVAL, "too many work items");
   if (items.size() > b->item_cap) {
+    // the old table (and every graph that points at it) goes away
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     free_graphs(b);
     if (b->d_items) (void)hipFree(b->d_items);
     b->d_items = nullptr;
@@ -1131,10 +1232,14 @@ int build_items(lbm_batch *b) {
     b->item_cap = cap;
   }
   b->nitems = (int)items.size();
-  HIP_TRY(hipMemcpy(b->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice),
-          "hipMemcpy(items)");
-  HIP_TRY(hipMemcpy(b->d_nitems, &b->nitems, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy(nitems)");
   return LBM_OK;
+}
+
+int build_items(lbm_batch *b) {
+  std::vector<int4> items;
+  int rc = make_items(b, items);
+  if (rc) return rc;
+  return upload_tables(b, nullptr, &items);
 }
 
 // Rebuild the tile table for a new member list; reuses the device buffers
@@ -1150,10 +1255,15 @@ int batch_set_members_impl(lbm_batch *b, lbm_handle *const *members, int32_t cou
     for (int64_t c0 = 0; c0 < cells; c0 += lbm::BATCH_TILE) tiles.push_back(make_int2(i, (int)c0));
   }
   if (tiles.size() > (size_t)0x7fffffff) return fail(LBM_EINVAL, "too many tiles");
-  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  for (int32_t i = 0; i < count; ++i) HIP_TRY(hipStreamSynchronize(members[i]->stream), "hipStreamSynchronize");
+  // work a member enqueued on another stream (its initialisation) must be
+  // done before the batch reads it; on the batch's own stream the order of
+  // the stream takes care of it
+  for (int32_t i = 0; i < count; ++i)
+    if (members[i]->stream != b->stream)
+      HIP_TRY(hipStreamSynchronize(members[i]->stream), "hipStreamSynchronize");
   if ((size_t)count > b->dom_cap || tiles.size() > b->tile_cap) {
     // grow: the old buffers (and every graph that points at them) go away
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     free_graphs(b);
     if (b->d_doms) (void)hipFree(b->d_doms);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
@@ -1185,16 +1295,15 @@ int batch_set_members_impl(lbm_batch *b, lbm_handle *const *members, int32_t cou
     b->tile_cap = tc;
   }
   b->ntiles = (int)tiles.size();
-  HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice),
-          "hipMemcpy(tiles)");
-  HIP_TRY(hipMemcpy(b->d_ntiles, &b->ntiles, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy(ntiles)");
   b->members.assign(members, members + count);
   b->storage = members[0]->user.storage;
-  // fresh trip slots for the new member list
+  // fresh trip slots for the new member list (stream-ordered)
   HIP_TRY(lbm::launch_fill_u64(b->d_trip, count, lbm::TRIP_NONE, b->stream), "detector slots");
-  HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   b->any_detector = false;
-  return build_items(b);
+  std::vector<int4> items;
+  rc = make_items(b, items);
+  if (rc) return rc;
+  return upload_tables(b, &tiles, &items);
 }
 
 // After a tick: one launch checks every member whose detector is due at
@@ -1256,7 +1365,8 @@ int lbm_batch_create(lbm_handle *const *members, int32_t count, void *stream,
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_ntiles, sizeof(int));
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_nitems, sizeof(int));
+  // item count and one ticket per strip launch of a tick (at most 4096 / 2)
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_nitems, sizeof(int) * (1 + 4096 / 2));
   // default shape: K-step strip launches (K = 4 for FP32, 3 for FP64 and FP16)
   b->storage = members[0]->user.storage;
   b->multi_k = b->storage == LBM_STORAGE_F32 ? 4 : 3;
@@ -1264,6 +1374,8 @@ int lbm_batch_create(lbm_handle *const *members, int32_t count, void *stream,
     e = hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming);
   for (int k = 0; k < 2 && e == hipSuccess; ++k)
     e = hipEventCreateWithFlags(&b->chk_copied[k], hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&b->tab_copied[k], hipEventDisableTiming);
   if (e != hipSuccess) {
     lbm_batch_destroy(b);
     return hip_fail(e, "lbm_batch_create");

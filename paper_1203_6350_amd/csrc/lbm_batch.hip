@@ -117,7 +117,7 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
 }
 
 hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
-                              const int4 *items, const int *nitems, int grid, int j,
+                              const int4 *items, int *nitems, int grid, int j,
                               hipStream_t stream) {
 #define LBM_BMULTI_K(ST)                                                                      \
   switch (k) {                                                                                \

@@ -84,7 +84,7 @@ hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void 
   hipError_t launch_multi_##ST##_k##K(const StepConfig &c, const void *src, void *dst,          \
                                       hipStream_t stream);                                       \
   hipError_t launch_batch_multi_##ST##_k##K(int nw, bool def, const BatchDomain *doms,          \
-                                            const int4 *items, const int *nitems, int grid,     \
+                                            const int4 *items, int *nitems, int grid,     \
                                             int j, hipStream_t stream);                          \
   int batch_multi_per_cu_##ST##_k##K(int nw, bool def);
 #define LBM_STRIP_DECL_K(ST) LBM_STRIP_DECL(ST, 2) LBM_STRIP_DECL(ST, 3) LBM_STRIP_DECL(ST, 4)
@@ -140,6 +140,11 @@ hipError_t launch_check_batch(int storage, const CheckDesc *descs_dev, int ndesc
                               int64_t max_cells, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
                            hipStream_t stream);
+hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t stream);
+// FP64 device profile (or NULL: zeros) -> n values of the storage's compute
+// type (FP64 for FP64 storage, FP32 otherwise).
+hipError_t launch_convert_profile(int storage, const double *src, void *dst, int64_t n,
+                                  hipStream_t stream);
 int elem_bytes_of(int storage);
 
 // Batched stepping (lbm_batch.hip). One descriptor per member domain.
@@ -165,10 +170,12 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
                         hipStream_t stream);
 // K = k steps (launch j of a tick) over the strip work items (int4: member,
 // first strip of the group, first row, rows), workgroups of nw waves.
+// nitems: device ints, [0] the item count, [1 + j] the item ticket of
+// launch j (zeroed before the launch).
 // def: every member has the default form's parameters (conserved rates 0,
 // n = m in the compute precision), which selects that form of the kernel.
 hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
-                              const int4 *items, const int *nitems, int grid, int j,
+                              const int4 *items, int *nitems, int grid, int j,
                               hipStream_t stream);
 int batch_multi_per_cu(int storage, int k, int nw, bool def);
 LBM_STRIP_DECL_K(f64)

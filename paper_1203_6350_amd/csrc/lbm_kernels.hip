@@ -836,6 +836,34 @@ __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long 
   if (i < n) p[i] = v;
 }
 
+__global__ void fill_i32_kernel(int *p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t stream) {
+  if (n < 1) return hipSuccess;
+  fill_i32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(p, n, v);
+  return hipGetLastError();
+}
+
+template <typename C>
+__global__ void convert_profile_kernel(const double *src, C *dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src ? C(src[i]) : C(0);
+}
+
+hipError_t launch_convert_profile(int storage, const double *src, void *dst, int64_t n,
+                                  hipStream_t stream) {
+  if (n < 1) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (storage == 0)
+    convert_profile_kernel<double><<<blocks, 256, 0, stream>>>(src, (double *)dst, n);
+  else
+    convert_profile_kernel<float><<<blocks, 256, 0, stream>>>(src, (float *)dst, n);
+  return hipGetLastError();
+}
+
 void fill_check_desc(const StepConfig &c, const void *lat, CheckDesc &d) {
   d.lat = lat;
   d.n = (int64_t)c.nx * c.ny;  // pitch == nx: the cells of a plane are contiguous

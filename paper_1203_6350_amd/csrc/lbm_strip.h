@@ -494,23 +494,40 @@ __global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K)) vo
   strip_run(c, min(rows_per_chunk, L.ny - Y0));
 }
 
-// Batched form: a persistent grid walks a table of work items (member
-// domain, first strip of a strip group, first row, rows); each workgroup
-// runs the strip loop of its item with the member's own size, rates,
-// variant, sponge and parity. Launch j of a tick advances the members that
-// take at least (j + 1) K steps in it.
+// Batched form: a persistent grid works through a table of work items
+// (member domain, first strip of a strip group, first row, rows); each
+// workgroup takes the next item with an atomic ticket (work[1 + j], zeroed
+// before the launch; work[0] holds the item count) and runs the strip loop
+// of its item with the member's own size, rates, variant, sponge and
+// parity. The table lists the tallest items first, so the short ones fill
+// the end of the launch. Launch j of a tick advances the members that take
+// at least (j + 1) K steps in it.
 // FP32 compute: registers for three waves per SIMD (the run-time variant
 // and rate switches would otherwise take it to two).
 // DEF: every member has the default form's parameters (collide's DEF).
 template <typename S, int K, bool DEF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
 void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restrict__ items,
-                       const int *__restrict__ nitems_dev, int j) {
+                       int *__restrict__ work, int j) {
   typedef typename Store<S>::C C;
-  const int nitems = *nitems_dev;
+  const int nitems = work[0];
+  int *ticket = work + 1 + j;
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
+  __shared__ int s_ticket;
+  for (;;) {
+    int t;
+    if (nw == 1) {
+      int v = 0;
+      if ((threadIdx.x & 63) == 0) v = atomicAdd(ticket, 1);
+      t = __builtin_amdgcn_readfirstlane(v);
+    } else {
+      if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1);
+      __syncthreads();
+      t = s_ticket;
+      __syncthreads();  // everyone has read it before the next ticket replaces it
+    }
+    if (t >= nitems) break;
     const int4 it = items[t];
     const BatchDomain &d = doms[it.x];
     if (j >= d.stop_at / K) continue;
@@ -636,7 +653,7 @@ static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void
 
 template <typename S, int K, bool DEF>
 static hipError_t launch_batch_multi_k(int nw, const BatchDomain *doms, const int4 *items,
-                                       const int *nitems, int grid, int j, hipStream_t s) {
+                                       int *nitems, int grid, int j, hipStream_t s) {
   if constexpr (strip_k_built<K>()) {
     batch_multi_strip<S, K, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j);
     return hipGetLastError();
@@ -646,7 +663,7 @@ static hipError_t launch_batch_multi_k(int nw, const BatchDomain *doms, const in
 
 template <typename S, bool DEF>
 static hipError_t launch_batch_multi_t(int k, int nw, const BatchDomain *doms, const int4 *items,
-                                       const int *nitems, int grid, int j, hipStream_t s) {
+                                       int *nitems, int grid, int j, hipStream_t s) {
   switch (k) {
     case 2: return launch_batch_multi_k<S, 2, DEF>(nw, doms, items, nitems, grid, j, s);
     case 3: return launch_batch_multi_k<S, 3, DEF>(nw, doms, items, nitems, grid, j, s);
@@ -658,7 +675,7 @@ static hipError_t launch_batch_multi_t(int k, int nw, const BatchDomain *doms, c
 // (Internal linkage: each translation unit builds its own step counts.)
 template <typename S>
 static hipError_t launch_batch_multi_storage(int k, int nw, bool def, const BatchDomain *doms,
-                                      const int4 *items, const int *nitems, int grid, int j,
+                                      const int4 *items, int *nitems, int grid, int j,
                                       hipStream_t s) {
   return def ? launch_batch_multi_t<S, true>(k, nw, doms, items, nitems, grid, j, s)
              : launch_batch_multi_t<S, false>(k, nw, doms, items, nitems, grid, j, s);

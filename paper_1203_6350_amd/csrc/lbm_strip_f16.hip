@@ -21,7 +21,7 @@ hipError_t LBM_CAT(launch_multi_f16_k, LBM_STRIP_ONLY_K)(const StepConfig &c, co
 hipError_t LBM_CAT(launch_batch_multi_f16_k, LBM_STRIP_ONLY_K)(int nw, bool def,
                                                                 const BatchDomain *doms,
                                                                 const int4 *items,
-                                                                const int *nitems, int grid,
+                                                                int *nitems, int grid,
                                                                 int j, hipStream_t stream) {
   return launch_batch_multi_storage<__half>(LBM_STRIP_ONLY_K, nw, def, doms, items, nitems, grid,
                                            j, stream);

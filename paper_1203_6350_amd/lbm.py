@@ -121,6 +121,7 @@ def load(path: str | None = None):
         "lbm_create_ext": [ctypes.POINTER(lbm_config), _DP, _DP, _DP, vp, vp, sz, ctypes.POINTER(_H)],
         "lbm_set_sponge": [_H, _DP, ctypes.POINTER(lbm_qref)],
         "lbm_set_sponge_separable": [_H, _DP, _DP, i32, ctypes.POINTER(lbm_qref)],
+        "lbm_set_sponge_separable_dev": [_H, vp, vp, i32, ctypes.POINTER(lbm_qref)],
         "lbm_step": [_H, i64],
         "lbm_sync": [_H],
         "lbm_moments": [_H, _DP, _DP, _DP],
@@ -287,6 +288,13 @@ def lbm_set_sponge_separable(h, chi_x=None, chi_y=None, combine="max", qref=None
     _b, pb = _host(chi_y)
     cm = COMBINE[combine] if isinstance(combine, str) else int(combine)
     _check(load().lbm_set_sponge_separable(h, pa, pb, cm, _qref(qref)))
+
+
+def lbm_set_sponge_separable_dev(h, chi_x=None, chi_y=None, combine="max", qref=None):
+    """Separable sponge from FP64 device tensors (or addresses); stream-ordered,
+    not validated."""
+    _check(load().lbm_set_sponge_separable_dev(h, _dev(chi_x), _dev(chi_y), COMBINE[combine],
+                                               _qref(qref)))
 
 
 def lbm_step(h, n=1):

@@ -172,3 +172,10 @@ def test_unstable_error_carries_the_result():
         lbm._check(lbm.LBM_EUNSTABLE, result=np.arange(7.0))
     assert isinstance(e.value, lbm.LbmUnstable) and e.value.code == lbm.LBM_EUNSTABLE
     np.testing.assert_array_equal(e.value.result, np.arange(7.0))
+
+
+def test_device_sponge_rejects_bad_arguments():
+    L = lbm.load()
+    q = lbm.lbm_qref(1.0, 0.0, 0.0)
+    assert L.lbm_set_sponge_separable_dev(None, None, None, 0, None) == lbm.LBM_EINVAL
+    assert "handle" in lbm.lbm_last_error()

@@ -246,6 +246,32 @@ def test_field_sponge_equals_separable_bitwise(storage):
     np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_device_sponge_profiles_equal_host_ones(storage):
+    """lbm_set_sponge_separable_dev (FP64 device profiles, stream-ordered)
+    gives the same bits as lbm_set_sponge_separable from host arrays, for
+    both combinations and a missing y profile."""
+    import torch
+    n = 72
+    rho, ux, uy, cx, u0 = meanflow_case(n)
+    q = (1.0, u0, 0.0)
+    cy = wl.quadratic_ramp_1d(n, 10, 0.35)
+    kw = dict(storage=storage, variant="II", ux_base=u0, f16_scale=5e-4)
+    for comb, py in (("max", cy), ("sum", cy), ("max", None)):
+        a = lbm.Lattice(n, n, rho=rho, ux=ux, uy=uy, **kw)
+        a.set_sponge_separable(cx, py, comb, q)
+        a.step(9)
+        b = lbm.Lattice(n, n, rho=rho, ux=ux, uy=uy, **kw)
+        dx = torch.from_numpy(cx).cuda()
+        dy = None if py is None else torch.from_numpy(py).cuda()
+        torch.cuda.synchronize()
+        lbm.lbm_set_sponge_separable_dev(b.h, dx, dy, comb, q)
+        b.step(9)
+        np.testing.assert_array_equal(a.save_state(), b.save_state())
+        a.close()
+        b.close()
+
+
 def test_moments_and_diagnostics_fp64():
     rho, ux, uy, chi = random_case(130, 70, 3)
     q = (1.0, 0.04, 0.0)

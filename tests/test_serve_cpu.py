@@ -29,6 +29,7 @@ class FakeExecutor:
         self.vn_delay = vn_delay
         self.resident = 0
         self.max_resident = 0
+        self.launched = []
 
     def footprint(self, req):
         return 72 * req.spec.nx * req.spec.ny
@@ -40,7 +41,7 @@ class FakeExecutor:
         self.max_resident = max(self.max_resident, self.resident)
         return {"f": oracle.feq_field(rho, ux, uy), "spec": sp}
 
-    def tick(self, states, steps, tick):
+    def launch(self, states, steps, tick, finishing):
         work = 0
         for st, n in zip(states, steps):
             sp = st["spec"]
@@ -48,10 +49,22 @@ class FakeExecutor:
                                   variant=sp.variant)
             work += n * sp.nx * sp.ny
         self.clock.t += work / self.lups
+        self.launched.append(([id(s) for s in states], list(steps)))
+        return {"finishing": list(finishing)}
 
-    def result(self, st):
-        self.resident -= 1
-        return {"diagnostics": oracle.diagnostics(st["f"], 1.0, st["spec"].u0, 0.0), "f": st["f"]}
+    def done(self, ticket):
+        return True
+
+    def wait(self, ticket):
+        pass
+
+    def results(self, ticket):
+        out = []
+        for st in ticket["finishing"]:
+            self.resident -= 1
+            out.append({"diagnostics": oracle.diagnostics(st["f"], 1.0, st["spec"].u0, 0.0),
+                        "f": st["f"]})
+        return out
 
     def vn_submit(self, req):
         return {"ready": self.clock.t + self.vn_delay}
@@ -84,6 +97,43 @@ def test_every_request_served_and_results_match_alone():
     s = st.summary(reqs)
     assert s["p50_ms"] <= s["p99_ms"]
     assert st.ticks > 0
+    # a finished domain takes no part in later ticks, and every domain takes
+    # exactly its requested steps
+    taken = {}
+    for ids, steps in ex.launched:
+        for i, n in zip(ids, steps):
+            assert n > 0
+            taken[i] = taken.get(i, 0) + n
+    assert sorted(taken.values()) == sorted(r.steps for r in reqs if r.kind == "domain")
+
+
+def test_pipelined_ticks_overlap_host_and_device():
+    """With two ticks in flight the server enqueues the next tick before it
+    waits for the previous one: an executor whose ticks complete only when
+    waited for sees a second launch before the first wait."""
+    clock = VirtualClock()
+
+    class Lazy(FakeExecutor):
+        def __init__(self, clock):
+            super().__init__(clock)
+            self.log = []
+
+        def launch(self, states, steps, tick, finishing):
+            self.log.append("launch")
+            return super().launch(states, steps, tick, finishing)
+
+        def done(self, ticket):
+            return False
+
+        def wait(self, ticket):
+            self.log.append("wait")
+
+    ex = Lazy(clock)
+    reqs = [r for r in small_requests(10, rate=1000.0, seed=5) if r.kind == "domain"]
+    srv = serve.Server(ex, budget_bytes=1 << 30, tick=4, clock=clock, sleep=clock.sleep)
+    srv.run(reqs)
+    assert all(r.t_done is not None for r in reqs)
+    assert ex.log[:2] == ["launch", "launch"]
 
 
 def test_admission_respects_budget_and_fifo():
