@@ -298,13 +298,19 @@ struct StripCtx {
   // Iteration at input row a (position P, taken mod 6): load what later
   // steps read of rows a + 1 (periodic row index r_next) and a + 2 (r_next2,
   // populations 4, 7, 8, which step 1 needs soonest), then steps 1..J at rows
-  // a - 1 .. a - J. left = iterations remaining including this one.
+  // a - 1 .. a - J.
+  //
+  // The loads are unconditional: near the end of the chunk they fetch up
+  // to three rows that no step reads (valid rows, the index wraps), but
+  // every iteration then issues the same memory operations, so each wait
+  // for a row's data waits for that row alone and not for the loads issued
+  // after it (a load behind a branch makes the wait drain them all).
   template <int P, int J>
-  __device__ __forceinline__ void iter(StripState<C, K> &st, int a, int r_next, int r_next2,
-                                       int left) const {
+  __device__ __forceinline__ void iter(StripState<C, K> &st, int a, int r_next,
+                                       int r_next2) const {
     if (nw > 1) __builtin_amdgcn_s_barrier();  // rows of the strip group in step
-    if (left > 2) load_478<P + 2>(st, r_next2);
-    if (left > 2) load_013<P + 1>(st, r_next);
+    load_478<P + 2>(st, r_next2);
+    load_013<P + 1>(st, r_next);
     // step 1 at row a - 1 from input rows a - 2, a - 1, a
     C g[9];
     {
@@ -312,10 +318,10 @@ struct StripCtx {
       pull<C>(st.a256[md<3>(P - 2)], st.a013[md<3>(P - 1)], rp[0], rp[1], rp[2], g);
     }
     // row a - 2's {2, 5, 6} are consumed: its slot takes row a + 1's
-    if (left > 3) load_256<P + 1>(st, r_next);
+    load_256<P + 1>(st, r_next);
     // the cell inputs of row a + 1 go to another ring slot than row a - 1's,
     // and are first needed in the next iteration
-    if (left > 2) row_inputs<P + 1>(st, r_next);
+    row_inputs<P + 1>(st, r_next);
     collide_at<P - 1>(st, g);
     chain<P, J, 2>(st, g, a);
   }
@@ -430,32 +436,32 @@ __device__ __forceinline__ void strip_run(const StripCtx<S, VAR, CHI, K> &c, int
   // from q = 2j on: q = 2, 3 run step 1, q = 4, 5 steps 1-2, q = 6, 7 steps
   // 1-3, and from q = 2K on all K steps run (R iterations).
   int a = c.Y0 - K + 2;
-  int left = R + 2 * K - 2;
   r = next(r);
-  c.template iter<2, 1>(st, a, r, next(r), left--);
+  c.template iter<2, 1>(st, a, r, next(r));
   ++a;
   r = next(r);
-  c.template iter<3, 1>(st, a, r, next(r), left--);
+  c.template iter<3, 1>(st, a, r, next(r));
   if constexpr (K >= 3) {
     ++a;
     r = next(r);
-    c.template iter<4, 2>(st, a, r, next(r), left--);
+    c.template iter<4, 2>(st, a, r, next(r));
     ++a;
     r = next(r);
-    c.template iter<5, 2>(st, a, r, next(r), left--);
+    c.template iter<5, 2>(st, a, r, next(r));
   }
   if constexpr (K >= 4) {
     ++a;
     r = next(r);
-    c.template iter<0, 3>(st, a, r, next(r), left--);
+    c.template iter<0, 3>(st, a, r, next(r));
     ++a;
     r = next(r);
-    c.template iter<1, 3>(st, a, r, next(r), left--);
+    c.template iter<1, 3>(st, a, r, next(r));
   }
+  int left = R;  // iterations with all K steps
 #define LBM_STRIP_ITER(PH)                                          \
   ++a;                                                              \
   r = next(r);                                                      \
-  c.template iter<(2 * K + PH) % 6, K>(st, a, r, next(r), left);    \
+  c.template iter<(2 * K + PH) % 6, K>(st, a, r, next(r));          \
   if (--left == 0) break;
   for (;;) {
     LBM_STRIP_ITER(0)
