@@ -341,13 +341,18 @@ const char *lbm_last_error(void);
  * remainder of fewer than K steps in a tick runs as one-step launches over
  * a table of 256-cell tiles. A batch whose work items do not fill the
  * device once (few or small members) runs its ticks as one-step tile
- * launches only, which spread it over the whole device. All members must share the storage mode and the
- * device; members with a per-cell reference state, a line source or rows
- * of more than 2^32 bytes are refused (LBM_EINVAL). Each member's result is bit-identical to stepping it alone with
- * lbm_step.
+ * launches only, which spread it over the whole device. All members must
+ * share the storage mode and the device. Members may carry a fixed per-cell
+ * reference state (lbm_set_qref_field; Sec. 2.2); members with a running-
+ * mean reference (lbm_set_qref_average with alpha != 0), a line source or
+ * rows of more than 2^32 bytes are refused (LBM_EINVAL), at creation and,
+ * for the first two, which can be set on a member later, at every tick
+ * before it enqueues anything. Each member's result is bit-identical to
+ * stepping it alone with lbm_step.
  * While a batch has work in flight its members must not be used on their
  * own; lbm_batch_sync makes them usable again. Member parameters (sponge,
- * q_ref, tuning) are read at every tick, so they may change between ticks.
+ * q_ref and its per-cell field, tuning) are read at every tick, so they may
+ * change between ticks.
  * The batch keeps pointers to the members: destroy the batch before them. */
 typedef struct lbm_batch lbm_batch;
 

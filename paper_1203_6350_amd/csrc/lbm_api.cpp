@@ -988,7 +988,7 @@ struct lbm_batch {
   int *d_nitems = nullptr;
   int nitems = 0;
   size_t item_cap = 0;
-  bool multi_def = false;  // every member takes the default form of the collision
+  int multi_form = 0;  // BATCH_DEF / BATCH_QF of the member list when the items were made
   // instability detector: per-member trip slots (one copy at lbm_batch_sync)
   // and the descriptors of one tick's checks, staged like the members'
   unsigned long long *d_trip = nullptr;            // [dom_cap]
@@ -1036,6 +1036,12 @@ void fill_domain(const lbm_handle *h, int stop_at, lbm::BatchDomain &d) {
     d.scale[i] = lbm::storage_scale(c, i);
     d.inv_scale[i] = 1.0 / d.scale[i];
   }
+  // a fixed per-cell reference; the undamped and viscosity-ramp variants
+  // ignore it, as alone
+  const bool damped = c.variant == LBM_VARIANT_I || c.variant == LBM_VARIANT_II ||
+                      c.variant == LBM_VARIANT_III;
+  d.qf = h->qf && damped ? h->qf : nullptr;
+  d.qps = h->qps;
 }
 
 // The member's parameters allow the collision's default form: conserved
@@ -1048,18 +1054,43 @@ bool default_form(const lbm::StepConfig &c) {
          (float)c.n == (float)c.m;
 }
 
+// What a batch cannot step: a line source (its per-step column override),
+// a running-mean reference (its second buffer follows the member's own
+// launches). Checked when the members are set and before every tick, since
+// both can be set on a member afterwards.
+int check_batchable(const lbm_handle *h, size_t i) {
+  if (h->channel)
+    return fail(LBM_EINVAL, "member " + std::to_string(i) + " has a line source; it is not batched");
+  if (h->qf && h->qalpha != 0.0)
+    return fail(LBM_EINVAL, "member " + std::to_string(i) +
+                                " has a running-mean reference state; batches take fixed ones");
+  return LBM_OK;
+}
+
+// The strip kernel's form for the current members.
+int batch_form(const std::vector<lbm_handle *> &members) {
+  bool def = true, qf = false;
+  for (const lbm_handle *h : members) {
+    def = def && default_form(h->cfg);
+    const int v = h->cfg.variant;
+    qf = qf || (h->qf && (v == LBM_VARIANT_I || v == LBM_VARIANT_II || v == LBM_VARIANT_III));
+  }
+  return (def ? lbm::BATCH_DEF : 0) | (qf ? lbm::BATCH_QF : 0);
+}
+
 void free_graphs(lbm_batch *b) {
   for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
 }
 
 // Instantiated graph of one tick: `nmulti` K-step strip launches
-// (j = 0 .. nmulti-1) then `nsingle` one-step tile launches (k = 0 ..
-// nsingle-1; with K-step launches these take the members' remainders).
-int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, hipGraphExec_t *out) {
+// (j = 0 .. nmulti-1, strip kernel form `form`) then `nsingle` one-step
+// tile launches (k = 0 .. nsingle-1; with K-step launches these take the
+// members' remainders).
+int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, int form, hipGraphExec_t *out) {
   const int grid = b->cus * b->blocks_per_cu;
   const auto key = std::make_tuple(K, nmulti, nsingle, b->blocks_per_cu, K ? b->multi_nw : 0,
-                                   K ? (int)b->multi_def : 0);
+                                   K ? form : 0);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -1071,7 +1102,7 @@ int batch_graph(lbm_batch *b, int K, int nmulti, int nsingle, hipGraphExec_t *ou
   // graph is replayed every tick)
   if (nmulti > 0) e = lbm::launch_fill_i32(b->d_nitems + 1, nmulti, 0, b->stream);
   for (int j = 0; j < nmulti && e == hipSuccess; ++j)
-    e = lbm::launch_batch_multi(b->storage, K, b->multi_nw, b->multi_def, b->d_doms,
+    e = lbm::launch_batch_multi(b->storage, K, b->multi_nw, form, b->d_doms,
                                 b->d_items, b->d_nitems, b->multi_grid, j, b->stream);
   for (int k = 0; k < nsingle && e == hipSuccess; ++k)
     e = lbm::launch_batch(b->storage, b->d_doms, b->d_tiles, b->d_ntiles, grid, k, K, b->stream);
@@ -1131,10 +1162,8 @@ int validate_members(lbm_handle *const *members, int32_t count) {
       return fail(LBM_EINVAL, "all members must live on one device");
     for (int32_t j = 0; j < i; ++j)
       if (members[j] == members[i]) return fail(LBM_EINVAL, "members must be distinct");
-    if (members[i]->qf)
-      return fail(LBM_EINVAL, "members with a per-cell reference state are not batched");
-    if (members[i]->channel)
-      return fail(LBM_EINVAL, "members with a line source are not batched");
+    int rc = check_batchable(members[i], (size_t)i);
+    if (rc) return rc;
     if (!lbm::strip_row_fits(members[i]->user.nx, members[i]->user.storage))
       return fail(LBM_EINVAL, "members with rows of more than 2^32 bytes are not batched");
   }
@@ -1192,9 +1221,8 @@ int make_items(lbm_batch *b, std::vector<int4> &items) {
   }
   const int W = 64 - 2 * b->multi_k;
   const int nw = b->multi_nw;
-  b->multi_def = true;
-  for (const lbm_handle *h : b->members) b->multi_def = b->multi_def && default_form(h->cfg);
-  const int per_cu = lbm::batch_multi_per_cu(b->storage, b->multi_k, nw, b->multi_def);
+  b->multi_form = batch_form(b->members);
+  const int per_cu = lbm::batch_multi_per_cu(b->storage, b->multi_k, nw, b->multi_form);
   if (per_cu < 1) return fail(LBM_EDEVICE, "the strip kernel does not fit on a compute unit");
   b->multi_grid = b->cus * per_cu;
   int64_t group_rows = 0;
@@ -1408,6 +1436,10 @@ int lbm_batch_set_tuning(lbm_batch *b, const lbm_tuning *t) {
   if (t->kernel >= 2) {
     if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
       return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512");
+    if (t->block > lbm::multi_step_max_block(b->storage, t->kernel))
+      return fail(LBM_EINVAL, "block must be at most " +
+                                  std::to_string(lbm::multi_step_max_block(b->storage, t->kernel)) +
+                                  " for this storage and step count");
     if (t->rows < 0 || t->rows > 4096) return fail(LBM_EINVAL, "rows must be 0 or 1..4096");
   }
   HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -1443,6 +1475,14 @@ int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
     for (size_t i = 0; i < n; ++i)
       if (member_steps[i] < 0 || member_steps[i] > tick)
         return fail(LBM_EINVAL, "member steps must lie in [0, tick]");
+  for (size_t i = 0; i < n; ++i) {
+    int rc = check_batchable(b->members[i], i);
+    if (rc) return rc;
+  }
+  // a reference field set on a member after the items were made selects
+  // that form now (the persistent grid, sized for the earlier form, takes
+  // its items by ticket whatever its residency)
+  const int form = batch_form(b->members);
   // descriptors go through one of two pinned staging buffers; the copy that
   // last read this buffer (two ticks ago) must have finished
   const int sl = b->slot;
@@ -1476,7 +1516,7 @@ int lbm_batch_tick(lbm_batch *b, int32_t tick, const int32_t *member_steps) {
     }
   }
   hipGraphExec_t ex = nullptr;
-  int rc = batch_graph(b, K, nmulti, nsingle, &ex);
+  int rc = batch_graph(b, K, nmulti, nsingle, form, &ex);
   if (rc) return rc;
   HIP_TRY(hipGraphLaunch(ex, b->stream), "hipGraphLaunch");
   for (size_t i = 0; i < n; ++i) {

@@ -83,6 +83,13 @@ __global__ __launch_bounds__(BX) void batch_step_kernel(
     p.dcf0 = C(d.dcf[0]);
     p.dcf1 = C(d.dcf[1]);
     p.dcf2 = C(d.dcf[2]);
+    if (d.qf) {  // the cell's own reference state (damped variants only)
+      const C *q = (const C *)d.qf;
+      const int64_t cell = r0 + x;
+      p.dcf0 = q[cell];
+      p.dcf1 = q[d.qps + cell];
+      p.dcf2 = q[2 * d.qps + cell];
+    }
     set_relax_coeffs(p);
     switch (d.variant) {
       case V_I: collide<C, V_I>(g, chi, p); break;
@@ -116,14 +123,14 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
+hipError_t launch_batch_multi(int storage, int k, int nw, int form, const BatchDomain *doms,
                               const int4 *items, int *nitems, int grid, int j,
                               hipStream_t stream) {
 #define LBM_BMULTI_K(ST)                                                                      \
   switch (k) {                                                                                \
-    case 2: return launch_batch_multi_##ST##_k2(nw, def, doms, items, nitems, grid, j, stream); \
-    case 3: return launch_batch_multi_##ST##_k3(nw, def, doms, items, nitems, grid, j, stream); \
-    case 4: return launch_batch_multi_##ST##_k4(nw, def, doms, items, nitems, grid, j, stream); \
+    case 2: return launch_batch_multi_##ST##_k2(nw, form, doms, items, nitems, grid, j, stream); \
+    case 3: return launch_batch_multi_##ST##_k3(nw, form, doms, items, nitems, grid, j, stream); \
+    case 4: return launch_batch_multi_##ST##_k4(nw, form, doms, items, nitems, grid, j, stream); \
   }                                                                                           \
   return hipErrorInvalidValue;
   switch (storage) {
@@ -135,12 +142,12 @@ hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchD
   return hipErrorInvalidValue;
 }
 
-int batch_multi_per_cu(int storage, int k, int nw, bool def) {
+int batch_multi_per_cu(int storage, int k, int nw, int form) {
 #define LBM_BPERCU_K(ST)                                        \
   switch (k) {                                                  \
-    case 2: return batch_multi_per_cu_##ST##_k2(nw, def);       \
-    case 3: return batch_multi_per_cu_##ST##_k3(nw, def);       \
-    case 4: return batch_multi_per_cu_##ST##_k4(nw, def);       \
+    case 2: return batch_multi_per_cu_##ST##_k2(nw, form);       \
+    case 3: return batch_multi_per_cu_##ST##_k3(nw, form);       \
+    case 4: return batch_multi_per_cu_##ST##_k4(nw, form);       \
   }                                                             \
   return 0;
   switch (storage) {

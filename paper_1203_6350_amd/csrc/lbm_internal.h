@@ -83,10 +83,10 @@ hipError_t launch_multi_steps(const StepConfig &c, int k, const void *src, void 
 #define LBM_STRIP_DECL(ST, K)                                                                    \
   hipError_t launch_multi_##ST##_k##K(const StepConfig &c, const void *src, void *dst,          \
                                       hipStream_t stream);                                       \
-  hipError_t launch_batch_multi_##ST##_k##K(int nw, bool def, const BatchDomain *doms,          \
+  hipError_t launch_batch_multi_##ST##_k##K(int nw, int form, const BatchDomain *doms,          \
                                             const int4 *items, int *nitems, int grid,     \
                                             int j, hipStream_t stream);                          \
-  int batch_multi_per_cu_##ST##_k##K(int nw, bool def);
+  int batch_multi_per_cu_##ST##_k##K(int nw, int form);
 #define LBM_STRIP_DECL_K(ST) LBM_STRIP_DECL(ST, 2) LBM_STRIP_DECL(ST, 3) LBM_STRIP_DECL(ST, 4)
 bool vec_supported(const StepConfig &c);
 // FP16 mode: stored value = deviation / storage_scale (a power of two).
@@ -161,7 +161,16 @@ struct BatchDomain {
   double n, m, rho_b, ubx, uby;
   double dcf[3];
   double scale[9], inv_scale[9];
+  // fixed per-cell reference state (compute type, [3][qps], rows of pitch),
+  // set for the damped variants when the member has one, else NULL
+  const void *qf;
+  int64_t qps;
 };
+// Forms of the batched strip kernel (bit mask): BATCH_DEF, every member has
+// the default form's parameters (conserved rates 0, n = m in the compute
+// precision); BATCH_QF, some member has a per-cell reference state.
+constexpr int BATCH_DEF = 1;
+constexpr int BATCH_QF = 2;
 // One step (launch k of a tick) over the tile table. kmulti = 0: the tick
 // runs as one-step launches only; kmulti = K: the tick's bulk ran as K-step
 // launches and this launch takes step k of each member's remainder.
@@ -172,12 +181,11 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
 // first strip of the group, first row, rows), workgroups of nw waves.
 // nitems: device ints, [0] the item count, [1 + j] the item ticket of
 // launch j (zeroed before the launch).
-// def: every member has the default form's parameters (conserved rates 0,
-// n = m in the compute precision), which selects that form of the kernel.
-hipError_t launch_batch_multi(int storage, int k, int nw, bool def, const BatchDomain *doms,
+// form: BATCH_DEF and BATCH_QF bits, which select that form of the kernel.
+hipError_t launch_batch_multi(int storage, int k, int nw, int form, const BatchDomain *doms,
                               const int4 *items, int *nitems, int grid, int j,
                               hipStream_t stream);
-int batch_multi_per_cu(int storage, int k, int nw, bool def);
+int batch_multi_per_cu(int storage, int k, int nw, int form);
 LBM_STRIP_DECL_K(f64)
 LBM_STRIP_DECL_K(f32)
 LBM_STRIP_DECL_K(f16)

@@ -508,11 +508,22 @@ __global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K)) vo
 // parity. The table lists the tallest items first, so the short ones fill
 // the end of the launch. Launch j of a tick advances the members that take
 // at least (j + 1) K steps in it.
-// FP32 compute: registers for three waves per SIMD (the run-time variant
-// and rate switches would otherwise take it to two).
+// Workgroups take at most multi_step_max_block threads, as the single-lattice
+// kernel. Waves per SIMD the registers are budgeted for: FP32 three (the
+// run-time variant and rate switches would otherwise take it to two), two
+// with per-cell references; FP16 (its round trips through the storage
+// format hold more values) two; FP64 one.
 // DEF: every member has the default form's parameters (collide's DEF).
-template <typename S, int K, bool DEF>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 3)))
+// QF: members may carry a fixed per-cell reference state (BatchDomain::qf,
+// set for the damped variants only); the form without it keeps the
+// registers of the uniform reference (18 fewer carried values).
+template <typename S, bool QF>
+constexpr int batch_waves_per_simd() {
+  return sizeof(S) == 8 ? 1 : (sizeof(S) == 2 || QF ? 2 : 3);
+}
+template <typename S, int K, bool DEF, bool QF>
+__global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K))
+__attribute__((amdgpu_waves_per_eu(batch_waves_per_simd<S, QF>())))
 void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restrict__ items,
                        int *__restrict__ work, int j) {
   typedef typename Store<S>::C C;
@@ -559,20 +570,34 @@ void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restr
     p.dcf1 = C(d.dcf[1]);
     p.dcf2 = C(d.dcf[2]);
     set_relax_coeffs(p);
-#define LBM_BATCH_RUN(VAR)                                                                   \
+#define LBM_BATCH_RUN(VAR, QFP)                                                              \
   {                                                                                          \
     StripCtx<S, VAR | (DEF ? V_DEF : 0), CHI_RUNTIME, K> c;                                  \
     strip_setup(c, (const S *)d.lat[par], (S *)d.lat[par ^ 1], d.nx, d.ny, d.pitch, d.ps,   \
                 strip, idle, it.z, nw, (const C *)d.chi_field, (const C *)d.chi_x,           \
-                (const C *)d.chi_y, d.chi_mode, scale, inv_scale, p);                        \
+                (const C *)d.chi_y, d.chi_mode, scale, inv_scale, p, QFP, d.qps);            \
     strip_run(c, it.w);                                                                      \
   }
-    switch (d.variant) {
-      case V_I: LBM_BATCH_RUN(V_I) break;
-      case V_II: LBM_BATCH_RUN(V_II) break;
-      case V_III: LBM_BATCH_RUN(V_III) break;
-      case V_VISC: LBM_BATCH_RUN(V_VISC) break;
-      default: LBM_BATCH_RUN(V_NONE) break;
+    bool ran = false;
+    if constexpr (QF) {
+      if (d.qf) {
+        const C *q = (const C *)d.qf;
+        ran = true;
+        switch (d.variant) {
+          case V_I: LBM_BATCH_RUN(V_I | V_QF, q) break;
+          case V_II: LBM_BATCH_RUN(V_II | V_QF, q) break;
+          default: LBM_BATCH_RUN(V_III | V_QF, q) break;
+        }
+      }
+    }
+    if (!ran) {
+      switch (d.variant) {
+        case V_I: LBM_BATCH_RUN(V_I, nullptr) break;
+        case V_II: LBM_BATCH_RUN(V_II, nullptr) break;
+        case V_III: LBM_BATCH_RUN(V_III, nullptr) break;
+        case V_VISC: LBM_BATCH_RUN(V_VISC, nullptr) break;
+        default: LBM_BATCH_RUN(V_NONE, nullptr) break;
+      }
     }
 #undef LBM_BATCH_RUN
     // the next item may belong to another member: no wave of this
@@ -657,61 +682,71 @@ static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void
   return hipErrorInvalidValue;
 }
 
-template <typename S, int K, bool DEF>
+template <typename S, int K, bool DEF, bool QF>
 static hipError_t launch_batch_multi_k(int nw, const BatchDomain *doms, const int4 *items,
                                        int *nitems, int grid, int j, hipStream_t s) {
   if constexpr (strip_k_built<K>()) {
-    batch_multi_strip<S, K, DEF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j);
+    batch_multi_strip<S, K, DEF, QF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
-template <typename S, bool DEF>
+template <typename S, bool DEF, bool QF>
 static hipError_t launch_batch_multi_t(int k, int nw, const BatchDomain *doms, const int4 *items,
                                        int *nitems, int grid, int j, hipStream_t s) {
   switch (k) {
-    case 2: return launch_batch_multi_k<S, 2, DEF>(nw, doms, items, nitems, grid, j, s);
-    case 3: return launch_batch_multi_k<S, 3, DEF>(nw, doms, items, nitems, grid, j, s);
-    case 4: return launch_batch_multi_k<S, 4, DEF>(nw, doms, items, nitems, grid, j, s);
+    case 2: return launch_batch_multi_k<S, 2, DEF, QF>(nw, doms, items, nitems, grid, j, s);
+    case 3: return launch_batch_multi_k<S, 3, DEF, QF>(nw, doms, items, nitems, grid, j, s);
+    case 4: return launch_batch_multi_k<S, 4, DEF, QF>(nw, doms, items, nitems, grid, j, s);
   }
   return hipErrorInvalidValue;
 }
 
 // (Internal linkage: each translation unit builds its own step counts.)
 template <typename S>
-static hipError_t launch_batch_multi_storage(int k, int nw, bool def, const BatchDomain *doms,
-                                      const int4 *items, int *nitems, int grid, int j,
-                                      hipStream_t s) {
-  return def ? launch_batch_multi_t<S, true>(k, nw, doms, items, nitems, grid, j, s)
-             : launch_batch_multi_t<S, false>(k, nw, doms, items, nitems, grid, j, s);
+static hipError_t launch_batch_multi_storage(int k, int nw, int form, const BatchDomain *doms,
+                                             const int4 *items, int *nitems, int grid, int j,
+                                             hipStream_t s) {
+  switch (form & (BATCH_DEF | BATCH_QF)) {
+    case BATCH_DEF: return launch_batch_multi_t<S, true, false>(k, nw, doms, items, nitems, grid, j, s);
+    case BATCH_DEF | BATCH_QF:
+      return launch_batch_multi_t<S, true, true>(k, nw, doms, items, nitems, grid, j, s);
+    case BATCH_QF: return launch_batch_multi_t<S, false, true>(k, nw, doms, items, nitems, grid, j, s);
+  }
+  return launch_batch_multi_t<S, false, false>(k, nw, doms, items, nitems, grid, j, s);
 }
 
-template <typename S, int K, bool DEF>
+template <typename S, int K, bool DEF, bool QF>
 static int batch_multi_per_cu_k(int nw) {
   int per_cu = 0;
   if constexpr (strip_k_built<K>()) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, K, DEF>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, K, DEF, QF>,
                                                      64 * nw, 0) != hipSuccess)
       return 0;
   }
   return per_cu;
 }
 
-template <typename S, bool DEF>
+template <typename S, bool DEF, bool QF>
 static int batch_multi_per_cu_t(int k, int nw) {
   switch (k) {
-    case 2: return batch_multi_per_cu_k<S, 2, DEF>(nw);
-    case 3: return batch_multi_per_cu_k<S, 3, DEF>(nw);
-    case 4: return batch_multi_per_cu_k<S, 4, DEF>(nw);
+    case 2: return batch_multi_per_cu_k<S, 2, DEF, QF>(nw);
+    case 3: return batch_multi_per_cu_k<S, 3, DEF, QF>(nw);
+    case 4: return batch_multi_per_cu_k<S, 4, DEF, QF>(nw);
   }
   return 0;
 }
 
 // Workgroups of nw waves of the batched multi-step kernel resident per CU.
 template <typename S>
-static int batch_multi_per_cu(int k, int nw, bool def) {
-  return def ? batch_multi_per_cu_t<S, true>(k, nw) : batch_multi_per_cu_t<S, false>(k, nw);
+static int batch_multi_per_cu(int k, int nw, int form) {
+  switch (form & (BATCH_DEF | BATCH_QF)) {
+    case BATCH_DEF: return batch_multi_per_cu_t<S, true, false>(k, nw);
+    case BATCH_DEF | BATCH_QF: return batch_multi_per_cu_t<S, true, true>(k, nw);
+    case BATCH_QF: return batch_multi_per_cu_t<S, false, true>(k, nw);
+  }
+  return batch_multi_per_cu_t<S, false, false>(k, nw);
 }
 
 // All variants, sponge forms and step counts of one storage type.

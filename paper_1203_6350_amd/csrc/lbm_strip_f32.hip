@@ -18,17 +18,17 @@ hipError_t LBM_CAT(launch_multi_f32_k, LBM_STRIP_ONLY_K)(const StepConfig &c, co
   return launch_multi_storage<float>(c, LBM_STRIP_ONLY_K, src, dst, stream);
 }
 
-hipError_t LBM_CAT(launch_batch_multi_f32_k, LBM_STRIP_ONLY_K)(int nw, bool def,
+hipError_t LBM_CAT(launch_batch_multi_f32_k, LBM_STRIP_ONLY_K)(int nw, int form,
                                                                 const BatchDomain *doms,
                                                                 const int4 *items,
                                                                 int *nitems, int grid,
                                                                 int j, hipStream_t stream) {
-  return launch_batch_multi_storage<float>(LBM_STRIP_ONLY_K, nw, def, doms, items, nitems, grid,
+  return launch_batch_multi_storage<float>(LBM_STRIP_ONLY_K, nw, form, doms, items, nitems, grid,
                                            j, stream);
 }
 
-int LBM_CAT(batch_multi_per_cu_f32_k, LBM_STRIP_ONLY_K)(int nw, bool def) {
-  return batch_multi_per_cu<float>(LBM_STRIP_ONLY_K, nw, def);
+int LBM_CAT(batch_multi_per_cu_f32_k, LBM_STRIP_ONLY_K)(int nw, int form) {
+  return batch_multi_per_cu<float>(LBM_STRIP_ONLY_K, nw, form);
 }
 
 }  // namespace lbm

@@ -158,8 +158,11 @@ def test_reference_field_round_trip_and_batch_refusal():
     lat.set_qref_field(*q)
     for a, b in zip(lat.qref_field(), q):
         np.testing.assert_allclose(a, b, rtol=1e-15, atol=1e-15)
+    lbm.Batch([lat]).close()  # a fixed field is batched, a running mean is not
+    lat.set_qref_average(0.25)
     with pytest.raises(lbm.LbmError):
         lbm.Batch([lat])
+    lat.set_qref_average(0.0)
     with pytest.raises(lbm.LbmError):
         lat.set_qref_average(1.5)
     lat.set_qref_field(None, None, None)
@@ -299,3 +302,112 @@ def test_autotune_keeps_running_mean_reference():
     assert (lat.save_state() == before[0]).all()
     assert np.array_equal(np.stack(lat.qref_field()), before[1])
     lat.close()
+
+
+# ------------------------------------------------------------ batches
+
+BATCH_SHAPES = [None, dict(kernel=0, block=256, rows=0), dict(kernel=2, block=128, rows=7),
+                dict(kernel=3, block=256, rows=0), dict(kernel=4, block=64, rows=5)]
+
+
+def batch_member(k, seed, rates):
+    """Ragged members of every variant; two in three carry a fixed per-cell
+    reference field; with rates, member 1 has non-zero conserved rates (the
+    batch then runs the general form of the collision)."""
+    g = np.random.default_rng(seed * 100 + k)
+    nx, ny = int(g.integers(3, 90)), int(g.integers(3, 70))
+    rho, ux, uy, chi, q = case(nx, ny, seed * 100 + k)
+    var = ("II", "I", "III", "none", "visc")[k % 5]
+    if var == "I":
+        chi = np.minimum(chi, 0.1)
+    if var == "visc":
+        chi = np.minimum(chi, 1.0)
+    s = (0.4, 0.3, 0.3) + (1.9,) * 6 if rates and k == 1 else None
+    return dict(nx=nx, ny=ny, rho=rho, ux=ux, uy=uy, chi=chi, q=q if k % 3 != 2 else None,
+                variant=var, s=s)
+
+
+def make_batch_member(m, storage):
+    kw = dict(s=m["s"]) if m["s"] is not None else {}
+    lat = lbm.Lattice(m["nx"], m["ny"], rho=m["rho"], ux=m["ux"], uy=m["uy"], storage=storage,
+                      variant=m["variant"], ux_base=0.04, f16_scale=1e-3, **kw)
+    lat.set_sponge(m["chi"], (1.0, 0.04, 0.0))
+    if m["q"] is not None:
+        lat.set_qref_field(*m["q"])
+    return lat
+
+
+@pytest.mark.parametrize("tuning", BATCH_SHAPES)
+@pytest.mark.parametrize("storage,rates", [("f64", False), ("f32", False), ("f16", False),
+                                           ("f64", True), ("f32", True)])
+def test_batch_with_reference_fields_equals_alone_bitwise(storage, rates, tuning):
+    """Members with a fixed per-cell reference field, batched beside members
+    without one: every batch launch shape (K-step strips of each K, one-step
+    tiles; 23 steps = whole launches plus a remainder) gives the bits of the
+    member stepped alone, in the default and the general form."""
+    say("case: batch with reference fields", storage, rates, tuning)
+    members = [batch_member(k, 7, rates) for k in range(10)]
+    alone = []
+    for m in members:
+        lat = make_batch_member(m, storage)
+        lat.step(23)
+        alone.append(lat.save_state())
+        lat.close()
+    lats = [make_batch_member(m, storage) for m in members]
+    b = lbm.Batch(lats)
+    if tuning is not None:
+        b.set_tuning(**tuning)
+    b.set_min_items(0)  # K-step launches even for this small batch
+    b.step(23)
+    b.sync()
+    for k, (lat, ref) in enumerate(zip(lats, alone)):
+        np.testing.assert_array_equal(lat.save_state(), ref, err_msg="member %d" % k)
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_takes_a_field_set_after_joining_and_refuses_a_running_mean():
+    """A field set on a member between ticks is used from the next tick on
+    (bitwise as alone); a running mean or a line source set on a member makes
+    the next tick fail before it enqueues anything, and clearing it lets the
+    batch go on."""
+    members = [batch_member(k, 8, False) for k in range(4)]
+    for m in members:
+        m["q"] = None
+    q = members[1]["q"] = case(members[1]["nx"], members[1]["ny"], 99)[4]
+    ref = make_batch_member(dict(members[1], q=None), "f32")
+    ref.step(5)
+    ref.set_qref_field(*q)
+    ref.step(9)
+    lats = [make_batch_member(dict(m, q=None), "f32") for m in members]
+    b = lbm.Batch(lats)
+    b.set_tuning(kernel=4, block=128, rows=0)
+    b.set_min_items(0)
+    b.step(5)
+    lats[1].set_qref_field(*q)
+    b.step(9)
+    b.sync()
+    np.testing.assert_array_equal(lats[1].save_state(), ref.save_state())
+    ref.close()
+    before = [lat.save_state() for lat in lats]
+    lats[2].set_qref_field(*case(members[2]["nx"], members[2]["ny"], 98)[4])
+    lats[2].set_qref_average(0.1)
+    with pytest.raises(lbm.LbmError) as e:
+        b.step(4)
+    assert "running-mean" in str(e.value)
+    for lat, st in zip(lats, before):  # nothing ran
+        np.testing.assert_array_equal(lat.save_state(), st)
+    lats[2].set_qref_average(0.0)
+    b.step(4)
+    b.sync()
+    lats[3].set_line_source((1.0, 1e-4, 0.05, 0.0, 0.0, 0.0))
+    with pytest.raises(lbm.LbmError) as e:
+        b.step(1)
+    assert "line source" in str(e.value)
+    lats[3].set_line_source(None)
+    b.step(2)
+    b.sync()
+    b.close()
+    for lat in lats:
+        lat.close()
