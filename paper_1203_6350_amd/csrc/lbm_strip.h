@@ -147,6 +147,8 @@ struct StripCtx {
   unsigned col;        // this lane's column
   unsigned col_bytes;  // col * sizeof(S)
   unsigned out_bytes;  // (lane - K) * sizeof(S): output offset from the strip start
+  unsigned row_bytes;  // bytes of a row's cells (the range of a row's loads)
+  unsigned out_range;  // bytes of the strip's outputs in a row (0: an idle wave)
   bool store_lane;
   int nw;              // waves per workgroup
   int nx, ny, Y0, X0;
@@ -168,45 +170,57 @@ struct StripCtx {
     r %= ny;
     return r < 0 ? r + ny : r;
   }
-  // global-memory views: elements move as same-size integers (the FP16
-  // element type is a class, which address-space pointers do not copy)
+  // Rows are read and written through buffer resources: a scalar
+  // descriptor (the row's address and byte range) plus the lane's 32-bit
+  // byte offset, which is never modified and so needs no copy per access
+  // (a global access with the scalar-base form needed one per load). An
+  // access at or past the range reads 0 or is dropped: a row's loads cover
+  // its nx cells, a row's stores the strip's own output columns. Stores are
+  // also lane-masked (store_lane): left to the range check alone, the halo
+  // lanes' addresses cost the memory-leaning two- and three-step shapes 4%.
+  // Elements move as same-size integers (the FP16 element type is a class).
   typedef typename std::conditional<
       sizeof(S) == 2, uint16_t,
       typename std::conditional<sizeof(S) == 4, uint32_t, uint64_t>::type>::type Bits;
-  typedef __attribute__((address_space(1))) Bits GS;
-  typedef __attribute__((address_space(1))) char GChar;
-  // The row's address is uniform across the wave; routing it through
-  // readfirstlane keeps it in scalar registers, so the load adds only the
-  // lane's 32-bit byte offset to it (no per-lane 64-bit addresses).
-  static __device__ __forceinline__ GChar *uniform_ptr(const void *p) {
-    const uint64_t u = (uint64_t)p;
-    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
-    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
-    return (GChar *)(lo | (hi << 32));
-  }
-  // The lane's byte offset is re-materialised at each use (an empty asm
-  // that emits nothing), so the 32-bit offset reaches the load itself and
-  // the instruction takes the scalar base + 32-bit vector offset form.
-  static __device__ __forceinline__ unsigned local(unsigned v) {
-    asm volatile("" : "+v"(v));
-    return v;
+  static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base,
+                                                                unsigned bytes) {
+    // raw access (stride 0); the third word is the gfx9-family default
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes,
+                                             0x00020000);
   }
   __device__ __forceinline__ C ld(int i, int r) const {
-    const GS *q =
-        (const GS *)(uniform_ptr(src + i * ps + (int64_t)r * pitch) + local(col_bytes));
-    const Bits b = *q;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(src + i * ps + (int64_t)r * pitch, row_bytes);
+    Bits b;
+    if constexpr (sizeof(S) == 2) {
+      b = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)col_bytes, 0, 0);
+    } else if constexpr (sizeof(S) == 4) {
+      b = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)col_bytes, 0, 0);
+    } else {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)col_bytes, 0, 0);
+      __builtin_memcpy(&b, &w, sizeof(b));
+    }
     S v;
     __builtin_memcpy(&v, &b, sizeof(S));
     return Store<S>::load(&v, scale[i]);
   }
-  // store of population i at this lane's output column of row y
+  // store of population i at this lane's output column of row y (only
+  // lanes with store_lane call it; the range drops anything else)
   __device__ __forceinline__ void st_out(int i, int y, C v) const {
-    GS *q = (GS *)(uniform_ptr(dst + i * ps + (int64_t)y * pitch + X0) + local(out_bytes));
+    const __amdgpu_buffer_rsrc_t rs = rsrc(dst + i * ps + (int64_t)y * pitch + X0, out_range);
     S t;
     Store<S>::store(&t, v, inv_scale[i]);
     Bits b;
     __builtin_memcpy(&b, &t, sizeof(S));
-    *q = b;
+    if constexpr (sizeof(S) == 2) {
+      __builtin_amdgcn_raw_buffer_store_b16(b, rs, (int)out_bytes, 0, 0);
+    } else if constexpr (sizeof(S) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(b, rs, (int)out_bytes, 0, 0);
+    } else {
+      // the 64-bit form takes a vector of two words
+      decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)) w;
+      __builtin_memcpy(&w, &b, sizeof(w));
+      __builtin_amdgcn_raw_buffer_store_b64(w, rs, (int)out_bytes, 0, 0);
+    }
   }
   // Sponge input of row r: the field value at this lane, or chi_y[r] of a
   // separable profile (combined with chi_x by chi_of when used).
@@ -344,7 +358,9 @@ struct StripCtx {
         if (store_lane) {
 #pragma unroll
           for (int i = 0; i < 9; ++i) st_out(i, a - K, o[i]);
-          if constexpr (QA) {
+        }
+        if constexpr (QA) {
+          if (store_lane) {
             const int64_t cell = (int64_t)(a - K) * pitch + X0 + (threadIdx.x & 63) - K;
             qf_out[cell] = st.qraw[md<6>(P - K)][0];
             qf_out[qps + cell] = st.qraw[md<6>(P - K)][1];
@@ -395,6 +411,11 @@ __device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S
   c.col = (unsigned)col;
   c.col_bytes = (unsigned)col * (unsigned)sizeof(S);
   c.out_bytes = (unsigned)(lane - K) * (unsigned)sizeof(S);
+  // a row holds at most 2^32 bytes (strip_row_fits): its last cell starts
+  // below 2^32 - sizeof(S), inside the largest range
+  const uint64_t rb = (uint64_t)nx * sizeof(S);
+  c.row_bytes = rb > 0xffffffffull ? 0xffffffffu : (unsigned)rb;
+  c.out_range = idle ? 0u : (unsigned)(min(W, nx - c.X0) * (int)sizeof(S));
   c.store_lane = !idle && lane >= K && lane < K + W && c.X0 + lane - K < nx;
   c.chi_mode = chi_mode;
   const int m = c.mode();
@@ -474,8 +495,18 @@ __device__ __forceinline__ void strip_run(const StripCtx<S, VAR, CHI, K> &c, int
 #undef LBM_STRIP_ITER
 }
 
+// Waves per SIMD the single-lattice kernel may run: the FP64 four-step form
+// one (its 245 registers would fit two, but the fitted chunks then halve in
+// height and the extra warm-up rows cost more than the second wave gains:
+// 0.530 against 0.539 ms per launch at 4096^2), the others unconstrained.
+template <typename S, int K>
+constexpr int strip_max_waves() {
+  return sizeof(S) == 8 && K == 4 ? 1 : 8;
+}
 template <typename S, int VAR, int CHI, int K>
-__global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K)) void step_multi_strip(
+__global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K))
+__attribute__((amdgpu_waves_per_eu(1, strip_max_waves<S, K>())))
+void step_multi_strip(
     const S *__restrict__ src, S *__restrict__ dst, Lat<S> L,
     CollideParams<typename Store<S>::C> p,
     const typename Store<S>::C *__restrict__ chi_field,
