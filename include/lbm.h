@@ -305,10 +305,11 @@ typedef struct lbm_tuning {
                           adjacent strips; the lattice is read and written
                           once per launch; a shorter remainder of steps
                           runs as one launch of that many steps, a single
-                          remaining step with kernel 0; rows of more than
-                          2^32 bytes (FP64, nx > 2^29) always run with
-                          kernel 0: the strips address columns with 32-bit
-                          byte offsets)                                      */
+                          remaining step with kernel 0; rows of 2^32
+                          bytes or more (FP64 with nx >= 2^29, FP32 with
+                          nx = 2^30) always run with kernel 0: the strips
+                          address a row with 32-bit byte offsets and
+                          ranges)                                            */
   int32_t block;       /* threads per block: 64, 128, 256 or 512 (FP64
                           storage with kernel 4: at most 256)               */
   int32_t nontemporal; /* 1: streaming stores (vector kernel only)           */
@@ -345,7 +346,7 @@ const char *lbm_last_error(void);
  * share the storage mode and the device. Members may carry a fixed per-cell
  * reference state (lbm_set_qref_field; Sec. 2.2); members with a running-
  * mean reference (lbm_set_qref_average with alpha != 0), a line source or
- * rows of more than 2^32 bytes are refused (LBM_EINVAL), at creation and,
+ * rows of 2^32 bytes or more are refused (LBM_EINVAL), at creation and,
  * for the first two, which can be set on a member later, at every tick
  * before it enqueues anything. Each member's result is bit-identical to
  * stepping it alone with lbm_step.

@@ -512,7 +512,7 @@ int lbm_step(lbm_handle *h, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   int64_t k = 0;
   const int per = h->cfg.kernel;  // time steps per launch of the multi-step kernel
-  // a channel, rows of more than 2^32 bytes, a running-mean reference state,
+  // a channel, rows of 2^32 bytes or more, a running-mean reference state,
   // or a per-cell one with parameters other than the default form run in the
   // one-step kernel only
   if (per >= lbm::KERNEL_MULTI_MIN && lbm::multi_step_supports(h->cfg)) {
@@ -1165,7 +1165,7 @@ int validate_members(lbm_handle *const *members, int32_t count) {
     int rc = check_batchable(members[i], (size_t)i);
     if (rc) return rc;
     if (!lbm::strip_row_fits(members[i]->user.nx, members[i]->user.storage))
-      return fail(LBM_EINVAL, "members with rows of more than 2^32 bytes are not batched");
+      return fail(LBM_EINVAL, "members with rows of 2^32 bytes or more are not batched");
   }
   return LBM_OK;
 }

@@ -49,11 +49,12 @@ enum { KERNEL_GENERIC = 0, KERNEL_VEC = 1, KERNEL_MULTI_MIN = 2, KERNEL_MULTI_MA
 constexpr int multi_step_max_block(int storage, int k) { return storage == 0 && k == 4 ? 256 : 512; }
 
 // The strip kernels address a lane's column within a row as a 32-bit byte
-// offset, so they take rows of at most 2^32 bytes (FP64 rows of more than
-// 2^29 cells run in the one-cell kernels).
+// offset and read a row through a buffer range of the row's byte count (a
+// 32-bit field), so they take rows of fewer than 2^32 bytes (FP64 rows of
+// 2^29 cells or more, FP32 rows of 2^30, run in the one-cell kernels).
 inline bool strip_row_fits(int64_t nx, int storage) {
   const int64_t eb = storage == 0 ? 8 : (storage == 1 ? 4 : 2);
-  return nx * eb <= (int64_t(1) << 32);
+  return nx * eb < (int64_t(1) << 32);
 }
 
 // The multi-step strip kernels take this configuration: rows that fit

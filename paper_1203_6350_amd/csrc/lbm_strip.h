@@ -411,10 +411,9 @@ __device__ __forceinline__ void strip_setup(StripCtx<S, VAR, CHI, K> &c, const S
   c.col = (unsigned)col;
   c.col_bytes = (unsigned)col * (unsigned)sizeof(S);
   c.out_bytes = (unsigned)(lane - K) * (unsigned)sizeof(S);
-  // a row holds at most 2^32 bytes (strip_row_fits): its last cell starts
-  // below 2^32 - sizeof(S), inside the largest range
-  const uint64_t rb = (uint64_t)nx * sizeof(S);
-  c.row_bytes = rb > 0xffffffffull ? 0xffffffffu : (unsigned)rb;
+  // a row holds fewer than 2^32 bytes (strip_row_fits): its byte count is
+  // the range
+  c.row_bytes = (unsigned)((uint64_t)nx * sizeof(S));
   c.out_range = idle ? 0u : (unsigned)(min(W, nx - c.X0) * (int)sizeof(S));
   c.store_lane = !idle && lane >= K && lane < K + W && c.X0 + lane - K < nx;
   c.chi_mode = chi_mode;
