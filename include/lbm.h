@@ -389,7 +389,8 @@ int lbm_batch_set_grid(lbm_batch *b, int32_t blocks_per_cu);
 /* Launch shape of the batch (see lbm_tuning): kernel 0 or 1 = one-step
  * launches over 256-cell tiles only (block and rows ignored); kernel 2, 3
  * or 4 = that many steps per launch of the strip kernel, `block` threads per
- * workgroup (64, 128, 256 or 512: adjacent strips of one member), `rows`
+ * workgroup (64, 128, 256 or 512, at most 256 for FP64 storage with 4 steps:
+ * adjacent strips of one member; LBM_EINVAL otherwise), `rows`
  * rows per work item (1..4096, or 0 for an automatic height: the member
  * rows over the resident workgroups, so that a launch has an item for each,
  * clamped to 8..64 rows). Default: K as above, block 128, rows 0. Rebuilds

@@ -800,6 +800,37 @@ def test_batch_small_batch_switches_to_tiles_bitwise():
         lat.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_workgroup_limit_per_storage(storage):
+    """A batch's strip workgroups take at most the single-lattice kernel's
+    block: 256 threads for the FP64 four-step kernel (one wave per SIMD),
+    512 otherwise; a larger block is refused and leaves the shape as it
+    was."""
+    members = batch_members(4, 31, storage)
+    lats = [make_member(m, storage) for m in members]
+    b = lbm.Batch(lats)
+    b.set_tuning(kernel=4, block=256, rows=0)
+    if storage == "f64":
+        with pytest.raises(lbm.LbmError) as e:
+            b.set_tuning(kernel=4, block=512, rows=0)
+        assert e.value.code == lbm.LBM_EINVAL
+        assert b.tuning()["block"] == 256
+        b.set_tuning(kernel=3, block=512, rows=0)
+    else:
+        b.set_tuning(kernel=4, block=512, rows=0)
+    b.set_min_items(0)
+    b.step(6)
+    b.sync()
+    for m, lat in zip(members, lats):
+        ref = make_member(m, storage)
+        ref.step(6)
+        np.testing.assert_array_equal(lat.save_state(), ref.save_state())
+        ref.close()
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
 @pytest.mark.parametrize("tuning", [None, dict(kernel=0, block=256, rows=0),
                                     dict(kernel=4, block=128, rows=3)])
 def test_batch_tick_partial_steps_and_oracle(tuning):
