@@ -495,7 +495,7 @@ __device__ __forceinline__ void strip_run(const StripCtx<S, VAR, CHI, K> &c, int
 }
 
 // Waves per SIMD the single-lattice kernel may run: the FP64 four-step form
-// one (its 245 registers would fit two, but the fitted chunks then halve in
+// one (its 253 registers would fit two, but the fitted chunks then halve in
 // height and the extra warm-up rows cost more than the second wave gains:
 // 0.530 against 0.539 ms per launch at 4096^2), the others unconstrained.
 template <typename S, int K>
