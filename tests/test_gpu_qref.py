@@ -385,6 +385,7 @@ def test_batch_takes_a_field_set_after_joining_and_refuses_a_running_mean():
     b.set_tuning(kernel=4, block=128, rows=0)
     b.set_min_items(0)
     b.step(5)
+    b.sync()  # members are the caller's again between a sync and the next tick
     lats[1].set_qref_field(*q)
     b.step(9)
     b.sync()
