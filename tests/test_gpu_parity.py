@@ -962,19 +962,22 @@ def test_plane_packet_2048_against_one_row_oracle(chi_max, storage, base):
         assert dR <= 1e-3 and dT <= 1e-3 and e_init <= 1e-3
 
 
-def test_full_size_4096_sampled_light_cone():
-    """The benchmark workload at full size (4096^2, FP32, Mach 0.2, 32 pulses,
-    64-cell sponge, Type II) in the benchmark's launch configuration: after T
-    steps, sampled cells (corners with the periodic wrap, sponge, interior
-    pulses) match the oracle run on the (4T+1)^2 neighbourhood that holds
-    their light cone."""
-    spec = wl.large_c2(variant="II", storage="f32")
+@pytest.mark.parametrize("storage,bar", [("f32", 1e-5), ("f64", 1e-9), ("f16", 1e-3)])
+def test_full_size_4096_sampled_light_cone(storage, bar):
+    """The benchmark workload at full size (4096^2, Mach 0.2, 32 pulses,
+    64-cell sponge, Type II) in each storage's autotuned launch shape (the
+    one the benchmark times): after T steps, sampled cells (corners with the
+    periodic wrap, sponge, interior pulses) match the oracle run on the
+    (4T+1)^2 neighbourhood that holds their light cone. FP64's bar is the
+    oracle's own rounding of full populations (about 1e-12 of the 1e-4
+    signal per operation) over T steps."""
+    spec = wl.large_c2(variant="II", storage=storage)
     T = 40
-    say("case: 4096^2 sampled light-cone parity, T =", T)
+    say("case: 4096^2 sampled light-cone parity", storage, "T =", T)
     rho, ux, uy = spec.fields()
     cx, cy = spec.chi_1d()
-    lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage="f32", variant="II",
-                      ux_base=spec.u0)
+    lat = lbm.Lattice(spec.nx, spec.ny, rho=rho, ux=ux, uy=uy, storage=storage, variant="II",
+                      ux_base=spec.u0, f16_scale=5e-4)
     lat.set_sponge_separable(cx, cy, "max", spec.qref)
     best, _ = lat.autotune(reps=3)
     say("  launch shape", best)
@@ -989,7 +992,7 @@ def test_full_size_4096_sampled_light_cone():
     centres += [(int(p[0]), int(p[1])) for p in spec.pulses[:4]]
     centres += [tuple(int(v) for v in g.integers(0, n, 2)) for _ in range(4)]
     num = den = 0.0
-    worst_abs = 0.0
+    worst_abs = peak = 0.0
     for (x0, y0) in centres:
         xs = (np.arange(x0 - H, x0 + H + 1)) % n
         ys = (np.arange(y0 - H, y0 + H + 1)) % n
@@ -1004,12 +1007,17 @@ def test_full_size_4096_sampled_light_cone():
         num += ((gp - rp) ** 2).sum()
         den += (rp ** 2).sum()
         worst_abs = max(worst_abs, np.abs(gp - rp).max())
+        peak = max(peak, np.abs(rp).max())
     # pooled over the samples (the pulse-centred patches carry the signal;
-    # far-field patches are zero to rounding on both sides)
+    # far-field patches are zero to rounding on both sides). The largest
+    # error at any sampled cell is held to 4x the bar of the largest p': a
+    # cell's density sums nine population roundings, and in FP16 one
+    # quantum of the stored scale (2^-11 of 2^-12 for w = 4/9 at f16_scale
+    # 5e-4) is already 5e-4 of this workload's p' peak after 40 steps
     e = math.sqrt(num / den)
-    say("  sampled p' rel L2 %.3e, max abs %.3e" % (e, worst_abs))
-    assert e <= 1e-5
-    assert worst_abs <= 1e-5 * 1e-4
+    say("  sampled p' rel L2 %.3e, max abs %.3e of peak %.3e" % (e, worst_abs, peak))
+    assert e <= bar
+    assert worst_abs <= 4 * bar * peak
 
 
 # ------------------------------------------------------------------ the paper's pulse comparison (Sec. 4.1)
