@@ -1069,13 +1069,14 @@ int check_batchable(const lbm_handle *h, size_t i) {
 
 // The strip kernel's form for the current members.
 int batch_form(const std::vector<lbm_handle *> &members) {
-  bool def = true, qf = false;
+  bool def = true, qf = false, mx = true;
   for (const lbm_handle *h : members) {
     def = def && default_form(h->cfg);
     const int v = h->cfg.variant;
     qf = qf || (h->qf && (v == LBM_VARIANT_I || v == LBM_VARIANT_II || v == LBM_VARIANT_III));
+    mx = mx && h->cfg.chi_mode == lbm::CHI_SEP_MAX;
   }
-  return (def ? lbm::BATCH_DEF : 0) | (qf ? lbm::BATCH_QF : 0);
+  return (def ? lbm::BATCH_DEF : 0) | (qf ? lbm::BATCH_QF : 0) | (mx ? lbm::BATCH_SEPMAX : 0);
 }
 
 void free_graphs(lbm_batch *b) {

@@ -169,9 +169,12 @@ struct BatchDomain {
 };
 // Forms of the batched strip kernel (bit mask): BATCH_DEF, every member has
 // the default form's parameters (conserved rates 0, n = m in the compute
-// precision); BATCH_QF, some member has a per-cell reference state.
+// precision); BATCH_QF, some member has a per-cell reference state;
+// BATCH_SEPMAX, every member's sponge is the separable max form (compiled
+// in, where otherwise the form is chosen per item at run time).
 constexpr int BATCH_DEF = 1;
 constexpr int BATCH_QF = 2;
+constexpr int BATCH_SEPMAX = 4;
 // One step (launch k of a tick) over the tile table. kmulti = 0: the tick
 // runs as one-step launches only; kmulti = K: the tick's bulk ran as K-step
 // launches and this launch takes step k of each member's remainder.
@@ -182,7 +185,8 @@ hipError_t launch_batch(int storage, const BatchDomain *doms, const int2 *tiles,
 // first strip of the group, first row, rows), workgroups of nw waves.
 // nitems: device ints, [0] the item count, [1 + j] the item ticket of
 // launch j (zeroed before the launch).
-// form: BATCH_DEF and BATCH_QF bits, which select that form of the kernel.
+// form: BATCH_DEF, BATCH_QF and BATCH_SEPMAX bits, which select that form of
+// the kernel.
 hipError_t launch_batch_multi(int storage, int k, int nw, int form, const BatchDomain *doms,
                               const int4 *items, int *nitems, int grid, int j,
                               hipStream_t stream);

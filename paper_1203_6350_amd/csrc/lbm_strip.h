@@ -547,11 +547,17 @@ void step_multi_strip(
 // QF: members may carry a fixed per-cell reference state (BatchDomain::qf,
 // set for the damped variants only); the form without it keeps the
 // registers of the uniform reference (18 fewer carried values).
+// MAXF: every member's sponge is the separable max form, compiled in. The
+// run-time choice of the form costs a test at every collision, which cuts
+// the loop into blocks and keeps the compiler from sharing 1/(1 + n chi)
+// between the steps of a row: 116.7 against 127 VALU per collision (Type
+// II), 166 against 160 GLUPS on 256 uneven members although the compiled-in
+// form spills 48-65 registers at three waves per SIMD.
 template <typename S, bool QF>
 constexpr int batch_waves_per_simd() {
   return sizeof(S) == 8 ? 1 : (sizeof(S) == 2 || QF ? 2 : 3);
 }
-template <typename S, int K, bool DEF, bool QF>
+template <typename S, int K, bool DEF, bool QF, bool MAXF>
 __global__ __launch_bounds__(multi_step_max_block(sizeof(S) == 8 ? 0 : 1, K))
 __attribute__((amdgpu_waves_per_eu(batch_waves_per_simd<S, QF>())))
 void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restrict__ items,
@@ -602,7 +608,7 @@ void batch_multi_strip(const BatchDomain *__restrict__ doms, const int4 *__restr
     set_relax_coeffs(p);
 #define LBM_BATCH_RUN(VAR, QFP)                                                              \
   {                                                                                          \
-    StripCtx<S, VAR | (DEF ? V_DEF : 0), CHI_RUNTIME, K> c;                                  \
+    StripCtx<S, VAR | (DEF ? V_DEF : 0), MAXF ? CHI_SEP_MAX : CHI_RUNTIME, K> c;           \
     strip_setup(c, (const S *)d.lat[par], (S *)d.lat[par ^ 1], d.nx, d.ny, d.pitch, d.ps,   \
                 strip, idle, it.z, nw, (const C *)d.chi_field, (const C *)d.chi_x,           \
                 (const C *)d.chi_y, d.chi_mode, scale, inv_scale, p, QFP, d.qps);            \
@@ -712,25 +718,34 @@ static hipError_t launch_multi(const StepConfig &c, int k, const void *src, void
   return hipErrorInvalidValue;
 }
 
-template <typename S, int K, bool DEF, bool QF>
+template <typename S, int K, bool DEF, bool QF, bool MAXF>
 static hipError_t launch_batch_multi_k(int nw, const BatchDomain *doms, const int4 *items,
                                        int *nitems, int grid, int j, hipStream_t s) {
   if constexpr (strip_k_built<K>()) {
-    batch_multi_strip<S, K, DEF, QF><<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j);
+    batch_multi_strip<S, K, DEF, QF, MAXF>
+        <<<dim3(grid), dim3(64 * nw), 0, s>>>(doms, items, nitems, j);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
-template <typename S, bool DEF, bool QF>
+template <typename S, bool DEF, bool QF, bool MAXF>
 static hipError_t launch_batch_multi_t(int k, int nw, const BatchDomain *doms, const int4 *items,
                                        int *nitems, int grid, int j, hipStream_t s) {
   switch (k) {
-    case 2: return launch_batch_multi_k<S, 2, DEF, QF>(nw, doms, items, nitems, grid, j, s);
-    case 3: return launch_batch_multi_k<S, 3, DEF, QF>(nw, doms, items, nitems, grid, j, s);
-    case 4: return launch_batch_multi_k<S, 4, DEF, QF>(nw, doms, items, nitems, grid, j, s);
+    case 2: return launch_batch_multi_k<S, 2, DEF, QF, MAXF>(nw, doms, items, nitems, grid, j, s);
+    case 3: return launch_batch_multi_k<S, 3, DEF, QF, MAXF>(nw, doms, items, nitems, grid, j, s);
+    case 4: return launch_batch_multi_k<S, 4, DEF, QF, MAXF>(nw, doms, items, nitems, grid, j, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <typename S, bool DEF, bool QF>
+static hipError_t launch_batch_multi_m(int k, int nw, bool mx, const BatchDomain *doms,
+                                       const int4 *items, int *nitems, int grid, int j,
+                                       hipStream_t s) {
+  return mx ? launch_batch_multi_t<S, DEF, QF, true>(k, nw, doms, items, nitems, grid, j, s)
+            : launch_batch_multi_t<S, DEF, QF, false>(k, nw, doms, items, nitems, grid, j, s);
 }
 
 // (Internal linkage: each translation unit builds its own step counts.)
@@ -738,45 +753,55 @@ template <typename S>
 static hipError_t launch_batch_multi_storage(int k, int nw, int form, const BatchDomain *doms,
                                              const int4 *items, int *nitems, int grid, int j,
                                              hipStream_t s) {
+  const bool mx = form & BATCH_SEPMAX;
   switch (form & (BATCH_DEF | BATCH_QF)) {
-    case BATCH_DEF: return launch_batch_multi_t<S, true, false>(k, nw, doms, items, nitems, grid, j, s);
+    case BATCH_DEF:
+      return launch_batch_multi_m<S, true, false>(k, nw, mx, doms, items, nitems, grid, j, s);
     case BATCH_DEF | BATCH_QF:
-      return launch_batch_multi_t<S, true, true>(k, nw, doms, items, nitems, grid, j, s);
-    case BATCH_QF: return launch_batch_multi_t<S, false, true>(k, nw, doms, items, nitems, grid, j, s);
+      return launch_batch_multi_m<S, true, true>(k, nw, mx, doms, items, nitems, grid, j, s);
+    case BATCH_QF:
+      return launch_batch_multi_m<S, false, true>(k, nw, mx, doms, items, nitems, grid, j, s);
   }
-  return launch_batch_multi_t<S, false, false>(k, nw, doms, items, nitems, grid, j, s);
+  return launch_batch_multi_m<S, false, false>(k, nw, mx, doms, items, nitems, grid, j, s);
 }
 
-template <typename S, int K, bool DEF, bool QF>
+template <typename S, int K, bool DEF, bool QF, bool MAXF>
 static int batch_multi_per_cu_k(int nw) {
   int per_cu = 0;
   if constexpr (strip_k_built<K>()) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_multi_strip<S, K, DEF, QF>,
-                                                     64 * nw, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, batch_multi_strip<S, K, DEF, QF, MAXF>, 64 * nw, 0) != hipSuccess)
       return 0;
   }
   return per_cu;
 }
 
-template <typename S, bool DEF, bool QF>
+template <typename S, bool DEF, bool QF, bool MAXF>
 static int batch_multi_per_cu_t(int k, int nw) {
   switch (k) {
-    case 2: return batch_multi_per_cu_k<S, 2, DEF, QF>(nw);
-    case 3: return batch_multi_per_cu_k<S, 3, DEF, QF>(nw);
-    case 4: return batch_multi_per_cu_k<S, 4, DEF, QF>(nw);
+    case 2: return batch_multi_per_cu_k<S, 2, DEF, QF, MAXF>(nw);
+    case 3: return batch_multi_per_cu_k<S, 3, DEF, QF, MAXF>(nw);
+    case 4: return batch_multi_per_cu_k<S, 4, DEF, QF, MAXF>(nw);
   }
   return 0;
+}
+
+template <typename S, bool DEF, bool QF>
+static int batch_multi_per_cu_m(int k, int nw, bool mx) {
+  return mx ? batch_multi_per_cu_t<S, DEF, QF, true>(k, nw)
+            : batch_multi_per_cu_t<S, DEF, QF, false>(k, nw);
 }
 
 // Workgroups of nw waves of the batched multi-step kernel resident per CU.
 template <typename S>
 static int batch_multi_per_cu(int k, int nw, int form) {
+  const bool mx = form & BATCH_SEPMAX;
   switch (form & (BATCH_DEF | BATCH_QF)) {
-    case BATCH_DEF: return batch_multi_per_cu_t<S, true, false>(k, nw);
-    case BATCH_DEF | BATCH_QF: return batch_multi_per_cu_t<S, true, true>(k, nw);
-    case BATCH_QF: return batch_multi_per_cu_t<S, false, true>(k, nw);
+    case BATCH_DEF: return batch_multi_per_cu_m<S, true, false>(k, nw, mx);
+    case BATCH_DEF | BATCH_QF: return batch_multi_per_cu_m<S, true, true>(k, nw, mx);
+    case BATCH_QF: return batch_multi_per_cu_m<S, false, true>(k, nw, mx);
   }
-  return batch_multi_per_cu_t<S, false, false>(k, nw);
+  return batch_multi_per_cu_m<S, false, false>(k, nw, mx);
 }
 
 // All variants, sponge forms and step counts of one storage type.

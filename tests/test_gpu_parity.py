@@ -730,6 +730,45 @@ def test_batch_equals_alone_bitwise(storage, tuning):
         lat.close()
 
 
+@pytest.mark.parametrize("tuning", [None, dict(kernel=2, block=128, rows=7),
+                                    dict(kernel=3, block=256, rows=0),
+                                    dict(kernel=4, block=64, rows=5)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_batch_all_separable_max_bitwise(storage, tuning):
+    """When every member's sponge is the separable max form the batch runs
+    the kernel with that form compiled in; adding one member with another
+    form switches it back to the run-time choice. Both equal the members
+    stepped alone, bit for bit (23 steps: whole launches and a remainder)."""
+    say("case: batch, all separable max", storage, tuning)
+    members = batch_members(12, 41, storage)
+    for m in members:
+        m["kind"] = 1
+    other = batch_members(1, 43, storage)[0]
+    other["kind"] = 2
+    alone = []
+    for m in members + [other]:
+        lat = make_member(m, storage)
+        lat.step(46 if m is not other else 23)
+        alone.append(lat.save_state())
+        lat.close()
+    lats = [make_member(m, storage) for m in members]
+    b = lbm.Batch(lats)
+    if tuning is not None:
+        b.set_tuning(**tuning)
+    b.set_min_items(0)
+    b.step(23)
+    b.sync()
+    extra = make_member(other, storage)
+    b.set_members(lats + [extra])
+    b.tick(23, np.full(len(lats) + 1, 23, dtype=np.int32))
+    b.sync()
+    for k, (lat, ref) in enumerate(zip(lats + [extra], alone)):
+        np.testing.assert_array_equal(lat.save_state(), ref, err_msg="member %d" % k)
+    b.close()
+    for lat in lats + [extra]:
+        lat.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_batch_default_form_switch_bitwise(storage):
     """The batched strip kernel has a form for members that all take the
