@@ -769,6 +769,56 @@ def test_batch_all_separable_max_bitwise(storage, tuning):
         lat.close()
 
 
+def test_full_batched_workload_sampled_against_oracle():
+    """The batched workload at full size (256 uneven domains, 64^2..512^2,
+    FP32, Types I/II/III, separable sponges, Mach 0..0.3) in the batch's
+    default launch shape, 100 steps: sampled members (the smallest ones of
+    each variant and two more) match the FP64 oracle run from the same
+    fields, p' within 1e-5 of the current p' (relative L2). Members that
+    the paper's condition s + chi > 2 makes unstable in Type I are left out
+    (the oracle diverges with them)."""
+    specs = wl.batch_c4()
+    T = 100
+    say("case: full batched workload, 256 domains, T =", T)
+    s = None
+    lats = [lbm.Lattice(sp.nx, sp.ny, rho=sp.fields()[0], ux=sp.fields()[1], uy=sp.fields()[2],
+                        storage=sp.storage, variant=sp.variant, s=sp.s,
+                        ux_base=sp.base_state[1]) for sp in specs]
+    for lat, sp in zip(lats, specs):
+        cx, cy = sp.chi_1d()
+        lat.set_sponge_separable(cx, cy, "max", sp.qref)
+    b = lbm.Batch(lats)
+    say("  batch shape", b.tuning())
+    b.step(T)
+    b.sync()
+
+    def stable(sp):
+        return sp.variant != "I" or sp.s[3] + sp.chi_max <= 2.0
+
+    order = sorted(range(len(specs)), key=lambda k: specs[k].nx * specs[k].ny)
+    picks = []
+    for var in ("I", "II", "III"):
+        picks += [k for k in order if specs[k].variant == var and stable(specs[k])][:2]
+    picks += [k for k in order[len(order) // 3:] if stable(specs[k])][:1]
+    worst = 0.0
+    for k in picks:
+        sp = specs[k]
+        rho, ux, uy = sp.fields()
+        ref = oracle.step(oracle.feq_field(rho, ux, uy), T, s=sp.s, chi=sp.chi_2d(),
+                          qref=sp.qref, variant=sp.variant)
+        rp = ref.sum(axis=0) - sp.rho0
+        gp = lats[k].moments()[0] - sp.rho0
+        e = np.sqrt(((gp - rp) ** 2).sum() / (rp ** 2).sum())
+        say("  member %d (%dx%d, %s, chi_max %.3f): p' rel L2 %.3e" % (
+            k, sp.nx, sp.ny, sp.variant, sp.chi_max, e))
+        worst = max(worst, e)
+    b.close()
+    for lat in lats:
+        lat.close()
+    assert len(picks) >= 6
+    assert worst <= 1e-5
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_batch_default_form_switch_bitwise(storage):
     """The batched strip kernel has a form for members that all take the
