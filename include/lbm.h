@@ -324,7 +324,10 @@ int lbm_get_tuning(lbm_handle *h, lbm_tuning *t);
 /* Time every candidate launch shape on the handle's own lattice (reps
  * launches each, after two warm-up launches; the state is not advanced),
  * keep the fastest and return it with its mean time per time step in ms.
- * best and best_ms may be NULL. Synchronises. */
+ * best and best_ms may be NULL. Synchronises. The timings depend on the
+ * current state: a field whose deviations are still mostly exact zeros
+ * (just initialised from localised pulses) runs faster and can rank the
+ * shapes differently from the developed field, so tune after some steps. */
 int lbm_autotune(lbm_handle *h, int32_t reps, lbm_tuning *best, double *best_ms);
 
 /* Release all resources of the handle; NULL is accepted. */
