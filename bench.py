@@ -537,6 +537,7 @@ def qref_leg(lbm, wl, torch, n=4096, steps=400, warmup=20, alpha=1e-3):
     cx, cy = sp.chi_1d()
     lat.set_sponge_separable(cx, cy, "max", sp.qref)
     lat.set_qref_field(rho, ux, uy)
+    lat.step(DEVELOP_STEPS)  # the autotuner below times a developed field
     out = {}
     for name, a, tune in (("alpha=0,one_cell", 0.0, "one"), ("alpha=0", 0.0, "auto"),
                           ("alpha=%g,one_cell" % alpha, alpha, "one"),
