@@ -705,6 +705,11 @@ def main():
               "a halo exchange) is designed but not built, so --gpus %d is not run." % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.steps < 4 or args.warmup < 0:
+        # the timed steps must hold at least one launch of the four-step
+        # kernel, whose mean duration the roofline divides by
+        print("bench.py: --steps must be at least 4 and --warmup at least 0", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     from paper_1203_6350_amd import lbm, workloads as wl

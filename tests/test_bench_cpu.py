@@ -18,6 +18,15 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and not r.stdout.strip()
 
 
+def test_too_few_steps_are_refused():
+    """Fewer timed steps than one launch of the four-step kernel would leave
+    no launch to time: refused with status 2 before any device work."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "--steps" in r.stderr and not r.stdout.strip()
+
+
 def test_summary_readers_take_only_profiled_shapes():
     """Counter figures are reported only for launch shapes that the
     committed summaries cover; any other shape reads as None (null in the
